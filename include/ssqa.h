@@ -1,0 +1,184 @@
+/*
+ * ssqa.h -- C ABI of the MI355X (gfx950) stochastic simulated quantum annealing library.
+ *
+ * The library anneals a fully connected integer Ising model
+ *     H(sigma) = - sum_i h_i sigma_i - sum_{i<j} J_ij sigma_i sigma_j          (paper, Eq. 1)
+ * with R Trotter replicas per trial coupled in a ring (Section 3.1, Eq. 4-5, Fig. 2) using the
+ * SSQA spin update (Section 3.2, Eq. 6a-c), on T independent trials at once.
+ *
+ * Integer model.  Every quantity is an integer at one scale S chosen by the caller: h, J, the noise
+ * amplitude n_rnd, J_perp(t), I_0(t) and alpha.  For a graph-isomorphism problem (Section 4) the
+ * coefficients are quarter-integers and J_perp moves in sixths, so S = 12 makes all of them exact;
+ * ssqa_gi_to_ising builds such a model.  All arithmetic is exact: a run is a deterministic function
+ * of (problem, parameters, seed).
+ *
+ * Random stream.  Philox4x32-10 (Salmon et al., SC'11) with key (low, high 32 bits of seed) and
+ * counter (tag, i >> 7, k, b): tag 0 gives the initial spins, tag t+1 the noise r(t) of the update
+ * t -> t+1; spin i uses bit (i & 31) of output word (i & 127) >> 5, and bit 1 means +1.  The result
+ * therefore does not depend on how the work is tiled or launched.
+ *
+ * Initial state: sigma(0) from tag 0, Is(0) = 0 where sigma = +1 and -alpha where sigma = -1, and
+ * sigma(t - d) = sigma(0) for t < d.
+ *
+ * Memory and streams.  Host arrays passed to ssqa_create_problem and the schedules are copied before
+ * the call returns; the caller keeps ownership.  Output arrays of ssqa_anneal and ssqa_energy are
+ * caller-owned DEVICE pointers on the problem's device.  ssqa_anneal and ssqa_energy are
+ * asynchronous with respect to the host on the given HIP stream (NULL = the default stream).
+ *
+ * Errors.  Every call returns an ssqa_status; nothing throws across the ABI.  On failure no output
+ * is written, and ssqa_last_error() returns a message for the calling thread.
+ */
+#ifndef SSQA_H
+#define SSQA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ssqa_status {
+    SSQA_OK = 0,
+    SSQA_EINVAL = -1,  /* invalid argument: null pointer, size or parameter out of range, J not symmetric */
+    SSQA_ENOMEM = -2,  /* device or host allocation failed */
+    SSQA_ERANGE = -3,  /* an int32 intermediate (field, counter sum, energy) could overflow */
+    SSQA_EDEVICE = -4, /* HIP runtime error: no device, launch or copy failure */
+    SSQA_ENOTSUP = -5  /* valid request outside what this build supports (e.g. R > 64) */
+} ssqa_status;
+
+/* Human-readable name of a status code (static storage). */
+const char* ssqa_status_string(ssqa_status s);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* ssqa_last_error(void);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Problem: the integer Ising model, resident on one device.                                   */
+/* ------------------------------------------------------------------------------------------- */
+
+typedef struct ssqa_problem* ssqa_problem_t;
+
+/*
+ * Copy an integer Ising model (paper, Eq. 1) to device `device` and prepare it for the sweep.
+ *   n_spins : N >= 1, at most 16384.
+ *   h       : host int32 [N], the spin biases h_i.
+ *   J       : host int32 [N * N] row-major, the couplings J_ij; must be symmetric with a zero
+ *             diagonal (only i != j pairs couple, Eq. 1 sums over i < j).
+ *   out     : receives the handle.
+ * J is stored as P signed int8 planes with J = sum_p 256^p J_p (P = 1 when every |J_ij| <= 127),
+ * zero-padded to a multiple of 128 rows and columns.
+ * Fails with SSQA_EINVAL for a bad size, pointer or non-symmetric J, and with SSQA_ERANGE when
+ * 2 * sum_i |h_i| + sum_ij |J_ij| >= 2^30 (energies and fields must stay inside int32).
+ */
+ssqa_status ssqa_create_problem(int32_t n_spins, const int32_t* h, const int32_t* J, int32_t device,
+                                ssqa_problem_t* out);
+
+/* Release the problem's device memory.  NULL is ignored.  No call may still be using it. */
+void ssqa_destroy_problem(ssqa_problem_t problem);
+
+/* N, the number of int8 planes P, and the padded size of the device layout. */
+int32_t ssqa_problem_spins(ssqa_problem_t problem);
+int32_t ssqa_problem_planes(ssqa_problem_t problem);
+int32_t ssqa_problem_padded(ssqa_problem_t problem);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Annealing.                                                                                  */
+/* ------------------------------------------------------------------------------------------- */
+
+#define SSQA_NO_TARGET INT64_MIN
+
+typedef struct ssqa_anneal_params {
+    int32_t replicas;          /* R >= 1 (Eq. 4); replica k couples to replica (k+1) mod R      */
+    int32_t trials;            /* T >= 1 independent trials                                     */
+    int32_t cycles;            /* SC >= 0 annealing cycles (updates of all N*R spins, Sec. 3.2) */
+    int32_t delay;             /* d in [0, 6]: the coupling reads sigma(t - d) (Eq. 6a)         */
+    int32_t alpha;             /* alpha >= 1: counter top is I_0 - alpha (Eq. 6b)               */
+    int32_t noise_amp;         /* n_rnd >= 0 at the integer scale (Eq. 6a)                      */
+    int32_t coupling_mode;     /* 0: J_perp(t) sigma_{i,k+1}(t-d) as printed in Eq. 6a;
+                                  1: J_perp(t) (sigma_{i,k-1}(t-d) + sigma_{i,k+1}(t-d))          */
+    int32_t cycles_per_launch; /* 0: all cycles in one persistent launch; k > 0: a host loop of
+                                  launches of at most k cycles (state kept in device memory)     */
+    const int32_t* jperp;      /* host int32 [cycles]: J_perp(t) at the integer scale           */
+    const int32_t* i0;         /* host int32 [cycles]: I_0(t), 1 <= alpha <= I_0(t) <= 127     */
+    uint64_t seed;             /* Philox key                                                    */
+    int64_t target_energy;     /* E* for first_hit, or SSQA_NO_TARGET                           */
+} ssqa_anneal_params;
+
+typedef struct ssqa_anneal_outputs {
+    int64_t* best_energy;      /* device int64 [T]: min over replicas and t in [0, SC] of H_p    */
+    int32_t* first_hit;        /* device int32 [T]: first t whose best replica has H_p == target,
+                                  -1 if never (or no target)                                    */
+    int32_t* energy_trace;     /* device int32 [(SC + 1) * T * R] or NULL: H_p of replica k of
+                                  trial b at cycle t at index (t * T + b) * R + k                */
+    int8_t* final_is;          /* device int8 [T * R * N] or NULL: Is(SC) at (b * R + k) * N + i */
+} ssqa_anneal_outputs;
+
+/*
+ * Run SSQA (paper, Section 3.2, Eq. 6a-c) for `cycles` cycles on `trials` independent trials of
+ * `replicas` coupled replicas, all N * R spins of a trial updated synchronously every cycle:
+ *   I  = h_i + sum_j J_ij sigma_{j,k}(t) + n_rnd r_{i,k}(t) + coupling
+ *   Is = I_0(t) - alpha if Is + I >= I_0(t);  -I_0(t) if Is + I < -I_0(t);  Is + I otherwise
+ *   sigma_{i,k}(t+1) = +1 if Is >= 0 else -1
+ * The problem Hamiltonian H_p (Eq. 5) of every replica is evaluated at t = 0 .. SC (one extra field
+ * pass after the last update) for best_energy, first_hit and the optional trace.
+ * Asynchronous on `stream`; the host schedules are copied before return.  Requires
+ * |J_perp(t)| <= 2^20 and n_rnd <= 2^20.  Returns SSQA_ENOTSUP for R > 64.
+ */
+ssqa_status ssqa_anneal(ssqa_problem_t problem, const ssqa_anneal_params* params,
+                        const ssqa_anneal_outputs* outputs, void* hip_stream);
+
+/*
+ * Problem Hamiltonian (Eq. 1 / Eq. 5) of `cols` spin configurations, exactly:
+ *   spins    : device int8 [cols * N], configuration c at c * N + i, entries +1 or -1.
+ *   energies : device int64 [cols].
+ * Asynchronous on `stream`.
+ */
+ssqa_status ssqa_energy(ssqa_problem_t problem, const int8_t* spins, int32_t cols, int64_t* energies,
+                        void* hip_stream);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Host helpers: schedules and the graph-isomorphism mapping (no device work).                 */
+/* ------------------------------------------------------------------------------------------- */
+
+/*
+ * J_perp schedule of Section 4.2 / Table 2, at the integer scale:
+ *   each iteration lasts tau * (beta + 1) cycles; J_perp starts it at jmin and rises by
+ *   (jmax - jmin) / beta every tau cycles, resetting to jmin when the next iteration starts.
+ * jmin = jmin_num / den and jmax = jmax_num / den in paper units; out[t] = scale * J_perp(t)
+ * must be an integer for every level (else SSQA_EINVAL).  out: host int32 [cycles].
+ */
+ssqa_status ssqa_jperp_schedule(int32_t cycles, int32_t tau, int32_t beta, int32_t jmin_num,
+                                int32_t jmax_num, int32_t den, int32_t scale, int32_t* out);
+
+/*
+ * I_0 schedule of SSA (Section 4.4): I_0 starts at i0_min, is multiplied by `growth` (= 1 / beta)
+ * every tau cycles up to i0_max, stays there for tau cycles and restarts at i0_min.
+ * out[t] = scale * I_0(t).  out: host int32 [cycles].
+ */
+ssqa_status ssqa_ssa_i0_schedule(int32_t cycles, int32_t tau, int32_t growth, int32_t i0_min,
+                                 int32_t i0_max, int32_t scale, int32_t* out);
+
+/*
+ * Graph isomorphism as an integer Ising model (Section 4.1, Eq. 8; mapping of Section 4.2).
+ *   a1, a2 : host uint8 [n * n] adjacency matrices (symmetric, zero diagonal) of graphs 1 and 2.
+ *   Spin p = u * n + i is x_{u,i} = 1 ("vertex u of graph 2 maps to vertex i of graph 1").
+ *   QUBO: Q_pp = -2 c1; for p < q: 2 c1 when exactly one of u == v, i == j holds; c2 when u != v,
+ *   i != j and a1[i][j] != a2[u][v] (each such unordered spin pair penalised once); else 0.
+ *   Ising at scale S (a multiple of 4): J_pq = -(S/4) Q_pq, h_p = -(S/2) Q_pp - (S/4) sum_q Q_pq.
+ *   h      : host int32 [n*n];  J : host int32 [n^4] row-major.
+ *   e_star : receives the scaled ground energy, reached exactly when x encodes an isomorphism.
+ */
+ssqa_status ssqa_gi_to_ising(int32_t n, const uint8_t* a1, const uint8_t* a2, int32_t c1, int32_t c2,
+                             int32_t scale, int32_t* h, int32_t* J, int64_t* e_star);
+
+/*
+ * The Philox4x32-10 block function used by the kernels, on the host, for verification:
+ * out = Philox4x32-10(counter ctr[0..3], key key[0..1]).
+ */
+void ssqa_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSQA_H */

@@ -97,10 +97,12 @@ def scaled(values, scale: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def field(J: np.ndarray, sigma: np.ndarray) -> np.ndarray:
-    """F[..., i] = sum_j J_ij sigma[..., j], exact (float64 product of small integers)."""
+    """F[..., i] = sum_j J_ij sigma[..., j], exact (float64 product of small integers;
+    J may be passed already converted to float64)."""
     shp = sigma.shape
     s2 = sigma.reshape(-1, shp[-1]).astype(np.float64)
-    F = s2 @ J.astype(np.float64).T
+    Jf = J if J.dtype == np.float64 else J.astype(np.float64)
+    F = s2 @ Jf.T
     return np.rint(F).astype(np.int64).reshape(shp)
 
 
@@ -219,6 +221,7 @@ def anneal(h, J, replicas: int, trials, cycles: int, jperp_sched, i0_sched, alph
     """
     h = np.asarray(h, dtype=np.int64)
     J = np.asarray(J, dtype=np.int64)
+    Jf = J.astype(np.float64)
     N = len(h)
     trial_ids = np.arange(trials) if np.isscalar(trials) else np.asarray(trials)
     if state is None:
@@ -230,7 +233,7 @@ def anneal(h, J, replicas: int, trials, cycles: int, jperp_sched, i0_sched, alph
     energies = []
     for t in range(t0, t0 + cycles + 1):
         sigma = hist[0]
-        F = field(J, sigma)
+        F = field(Jf, sigma)
         energies.append(energy_from_field(h, sigma, F))
         if t == t0 + cycles:
             break

@@ -1,0 +1,21 @@
+"""MI355X-native stochastic simulated quantum annealing (SSQA).
+
+The sweep (Eq. 6a-c of the paper) runs in hand-written gfx950 HIP kernels in
+libssqa.so behind the C ABI of include/ssqa.h; ``api`` is its Python binding.
+Importing the package does not load the library; the first call does, and fails
+loudly if it has not been built.
+"""
+
+from .api import (  # noqa: F401
+    SSQA_NO_TARGET,
+    AnnealResult,
+    Problem,
+    SSQAError,
+    ssqa_anneal,
+    ssqa_create_problem,
+    ssqa_energy,
+    ssqa_gi_to_ising,
+    ssqa_jperp_schedule,
+    ssqa_philox4x32_10,
+    ssqa_ssa_i0_schedule,
+)

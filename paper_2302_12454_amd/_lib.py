@@ -1,0 +1,80 @@
+"""ctypes declarations of the C ABI in include/ssqa.h (libssqa.so, built in-tree)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssqa.so")
+
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+c_int64_p = ctypes.POINTER(ctypes.c_int64)
+c_uint32_p = ctypes.POINTER(ctypes.c_uint32)
+c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class AnnealParams(ctypes.Structure):
+    _fields_ = [
+        ("replicas", ctypes.c_int32),
+        ("trials", ctypes.c_int32),
+        ("cycles", ctypes.c_int32),
+        ("delay", ctypes.c_int32),
+        ("alpha", ctypes.c_int32),
+        ("noise_amp", ctypes.c_int32),
+        ("coupling_mode", ctypes.c_int32),
+        ("cycles_per_launch", ctypes.c_int32),
+        ("jperp", c_int32_p),
+        ("i0", c_int32_p),
+        ("seed", ctypes.c_uint64),
+        ("target_energy", ctypes.c_int64),
+    ]
+
+
+class AnnealOutputs(ctypes.Structure):
+    _fields_ = [
+        ("best_energy", ctypes.c_void_p),
+        ("first_hit", ctypes.c_void_p),
+        ("energy_trace", ctypes.c_void_p),
+        ("final_is", ctypes.c_void_p),
+    ]
+
+
+# Every symbol include/ssqa.h declares, with (restype, argtypes).
+SIGNATURES = {
+    "ssqa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ssqa_last_error": (ctypes.c_char_p, []),
+    "ssqa_create_problem": (ctypes.c_int, [ctypes.c_int32, c_int32_p, c_int32_p, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "ssqa_destroy_problem": (None, [ctypes.c_void_p]),
+    "ssqa_problem_spins": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ssqa_problem_planes": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ssqa_problem_padded": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ssqa_anneal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams),
+                                   ctypes.POINTER(AnnealOutputs), ctypes.c_void_p]),
+    "ssqa_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "ssqa_jperp_schedule": (ctypes.c_int, [ctypes.c_int32] * 7 + [c_int32_p]),
+    "ssqa_ssa_i0_schedule": (ctypes.c_int, [ctypes.c_int32] * 6 + [c_int32_p]),
+    "ssqa_gi_to_ising": (ctypes.c_int, [ctypes.c_int32, c_uint8_p, c_uint8_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, c_int32_p, c_int32_p, c_int64_p]),
+    "ssqa_philox4x32_10": (None, [c_uint32_p, c_uint32_p, c_uint32_p]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libssqa.so; raises ImportError when it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,192 @@
+"""Python binding of the SSQA C ABI (include/ssqa.h): argument marshalling only.
+
+Every computation runs in libssqa.so: the sweep, the energies and the plane split
+in HIP kernels on the GPU, the schedules and the GI mapping in the library's
+host code.  PyTorch supplies device memory and the current HIP stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+
+SSQA_NO_TARGET = -(2 ** 63)
+
+
+class SSQAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _lib.load()
+        name = lib.ssqa_status_string(status).decode()
+        msg = lib.ssqa_last_error().decode()
+        super().__init__(f"{where}: {name}: {msg}")
+        self.status = status
+        self.name = name
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise SSQAError(status, where)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class Problem:
+    """An integer Ising model resident on one device (ssqa_create_problem)."""
+
+    def __init__(self, h, J, device: int = 0):
+        lib = _lib.load()
+        h = _i32(h)
+        J = _i32(J)
+        n = int(h.shape[0])
+        if J.shape != (n, n):
+            raise ValueError(f"J must be {n} x {n}")
+        handle = ctypes.c_void_p()
+        _check(lib.ssqa_create_problem(n, _ptr(h, ctypes.c_int32), _ptr(J, ctypes.c_int32), int(device),
+                                       ctypes.byref(handle)), "ssqa_create_problem")
+        self._handle = handle
+        self.device = int(device)
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._handle
+
+    @property
+    def planes(self) -> int:
+        return int(_lib.load().ssqa_problem_planes(self._handle))
+
+    @property
+    def padded(self) -> int:
+        return int(_lib.load().ssqa_problem_padded(self._handle))
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _lib.load().ssqa_destroy_problem(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ssqa_create_problem(h, J, device: int = 0) -> Problem:
+    return Problem(h, J, device)
+
+
+@dataclass
+class AnnealResult:
+    best_energy: "object"          # torch int64 [T] on the device
+    first_hit: "object"            # torch int32 [T]
+    energy_trace: "object | None"  # torch int32 [SC + 1, T, R]
+    final_is: "object | None"      # torch int8 [T, R, N]
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
+                noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
+                trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, stream=None,
+                out: AnnealResult | None = None) -> AnnealResult:
+    """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
+    current stream).  ``out`` may carry preallocated outputs of the right shapes."""
+    import torch
+    lib = _lib.load()
+    dev = torch.device("cuda", problem.device)
+    jperp = _i32(jperp)
+    i0 = _i32(i0)
+    if len(jperp) < cycles or len(i0) < cycles:
+        raise ValueError("schedules shorter than cycles")
+    if out is None:
+        out = AnnealResult(
+            best_energy=torch.empty(trials, dtype=torch.int64, device=dev),
+            first_hit=torch.empty(trials, dtype=torch.int32, device=dev),
+            energy_trace=(torch.empty((cycles + 1, trials, replicas), dtype=torch.int32, device=dev)
+                          if trace else None),
+            final_is=(torch.empty((trials, replicas, problem.n), dtype=torch.int8, device=dev)
+                      if final_is else None),
+        )
+    p = _lib.AnnealParams()
+    p.replicas, p.trials, p.cycles = int(replicas), int(trials), int(cycles)
+    p.delay, p.alpha, p.noise_amp = int(delay), int(alpha), int(noise_amp)
+    p.coupling_mode, p.cycles_per_launch = int(coupling_mode), int(cycles_per_launch)
+    p.jperp = _ptr(jperp, ctypes.c_int32)
+    p.i0 = _ptr(i0, ctypes.c_int32)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    p.target_energy = SSQA_NO_TARGET if target is None else int(target)
+    o = _lib.AnnealOutputs()
+    o.best_energy = out.best_energy.data_ptr()
+    o.first_hit = out.first_hit.data_ptr()
+    o.energy_trace = out.energy_trace.data_ptr() if out.energy_trace is not None else None
+    o.final_is = out.final_is.data_ptr() if out.final_is is not None else None
+    _check(lib.ssqa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
+           "ssqa_anneal")
+    return out
+
+
+def ssqa_energy(problem: Problem, spins, stream=None):
+    """H_p of each row of ``spins`` (torch int8 [cols, N] of +-1 on the device) -> int64 [cols]."""
+    import torch
+    lib = _lib.load()
+    spins = spins.contiguous()
+    if spins.dtype != torch.int8 or spins.dim() != 2 or spins.shape[1] != problem.n:
+        raise ValueError("spins must be int8 [cols, N]")
+    cols = int(spins.shape[0])
+    energies = torch.empty(cols, dtype=torch.int64, device=spins.device)
+    _check(lib.ssqa_energy(problem.handle, ctypes.c_void_p(spins.data_ptr()), cols,
+                           ctypes.c_void_p(energies.data_ptr()), _stream_handle(stream)), "ssqa_energy")
+    return energies
+
+
+def ssqa_jperp_schedule(cycles: int, tau: int, beta: int, jmin_num: int, jmax_num: int, den: int,
+                        scale: int) -> np.ndarray:
+    out = np.zeros(max(cycles, 1), dtype=np.int32)
+    _check(_lib.load().ssqa_jperp_schedule(cycles, tau, beta, jmin_num, jmax_num, den, scale,
+                                           _ptr(out, ctypes.c_int32)), "ssqa_jperp_schedule")
+    return out[:cycles]
+
+
+def ssqa_ssa_i0_schedule(cycles: int, tau: int, growth: int, i0_min: int, i0_max: int, scale: int) -> np.ndarray:
+    out = np.zeros(max(cycles, 1), dtype=np.int32)
+    _check(_lib.load().ssqa_ssa_i0_schedule(cycles, tau, growth, i0_min, i0_max, scale,
+                                            _ptr(out, ctypes.c_int32)), "ssqa_ssa_i0_schedule")
+    return out[:cycles]
+
+
+def ssqa_gi_to_ising(a1, a2, c1: int = 1, c2: int = 1, scale: int = 12):
+    """GI pair -> (h int32 [N], J int32 [N, N], E* int) computed by the library."""
+    a1 = np.ascontiguousarray(np.asarray(a1, dtype=np.uint8))
+    a2 = np.ascontiguousarray(np.asarray(a2, dtype=np.uint8))
+    n = a1.shape[0]
+    N = n * n
+    h = np.zeros(N, dtype=np.int32)
+    J = np.zeros((N, N), dtype=np.int32)
+    e = ctypes.c_int64()
+    _check(_lib.load().ssqa_gi_to_ising(n, _ptr(a1, ctypes.c_uint8), _ptr(a2, ctypes.c_uint8), c1, c2, scale,
+                                        _ptr(h, ctypes.c_int32), _ptr(J, ctypes.c_int32), ctypes.byref(e)),
+           "ssqa_gi_to_ising")
+    return h, J, int(e.value)
+
+
+def ssqa_philox4x32_10(ctr, key) -> list[int]:
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    _lib.load().ssqa_philox4x32_10(c, k, o)
+    return [int(x) for x in o]

@@ -1,0 +1,62 @@
+// Internal interfaces between the C ABI (api.cpp) and the HIP kernels (sweep.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssqa {
+
+// Rows per tile: one Philox output block covers 128 consecutive spins of one replica.
+constexpr int kTileRows = 128;
+// K extent of one int8 MFMA (v_mfma_i32_16x16x64_i8).
+constexpr int kStepK = 64;
+// Largest delay d supported (bit-plane ring of d + 2 planes in LDS).
+constexpr int kMaxDelay = 6;
+
+// Device-side description of one problem.
+struct DeviceProblem {
+    int32_t n;          // spins N
+    int32_t np;         // N padded to a multiple of kTileRows (rows and columns of every plane)
+    int32_t planes;     // P int8 planes, J = sum_p 256^p J_p
+    const int8_t* J;    // [P][np][np] row-major, zero padded
+    const int32_t* h;   // [np], zero padded
+    const int32_t* rowsum;  // [np]: sum_j J_ij
+};
+
+// Arguments of one launch of the persistent sweep kernel.
+struct SweepArgs {
+    DeviceProblem prob;
+    int32_t R;              // replicas
+    int32_t T;              // trials
+    int32_t tpw;            // trials per workgroup
+    int32_t cols_wg;        // tpw * R <= columns per workgroup
+    int32_t t_begin;        // first cycle of this launch (absolute)
+    int32_t t_end;          // cycles [t_begin, t_end) are updated in this launch
+    int32_t final_pass;     // evaluate H_p at t_end as well (last launch of a run)
+    int32_t delay;
+    int32_t alpha;
+    int32_t noise_amp;
+    int32_t mode;
+    uint32_t key0, key1;
+    int64_t target;         // INT64_MIN for none
+    const int32_t* jperp;   // device [cycles] indexed by absolute t
+    const int32_t* i0;      // device [cycles]
+    int8_t* is_state;       // [n_wg * NB][np]: counters, column = wg * NB + local column
+    uint32_t* hist_state;   // [n_wg][delay][NB][np / 32]: sigma(t_begin - s) bits, s = 1..d
+    int64_t* best;          // [T]
+    int32_t* first_hit;     // [T]
+    int32_t* trace;         // [(SC + 1)][T * R] or nullptr; row t holds cycle t
+};
+
+// Launchers (sweep.hip).  Return hipSuccess or the launch error.
+hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
+                                 int8_t* Jp, int32_t* h_pad, int32_t* rowsum, hipStream_t stream);
+int sweep_columns_per_wg();
+size_t sweep_lds_bytes(int np, int delay);
+hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
+hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T,
+                                int32_t tpw, int8_t* out, hipStream_t stream);
+hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t cols, int64_t* energies,
+                         hipStream_t stream);
+
+}  // namespace ssqa

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP sweep against the oracle, bit for bit, through the C ABI."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ssqa
+from synth import random_ising
+from tests.parity_util import assert_same, gi_case, paper_schedules, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2302_12454_amd as lib
+    return lib
+
+
+def test_gi5_full_small_case(lib):
+    """N = 25 GI (G(5, 0.5) with graph seed 0 and its relabelled copy), R = 8, 500 cycles,
+    100 trials, Philox seed 0: every energy, best, first hit and final counter."""
+    _note("case gi5 N=25 R=8 T=100 SC=500")
+    h, J, e_star = gi_case(5, 0)
+    q, i0, noise = paper_schedules(500)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=8, trials=100, cycles=500, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=0,
+              target=e_star)
+    gpu = run_gpu(prob, **kw)
+    ref = run_oracle(h, J, **kw)
+    assert_same(gpu, ref)
+    assert (gpu["first_hit"] >= 0).mean() > 0.9
+
+
+@pytest.mark.parametrize("n,R,T,SC,delay,mode,seed", [
+    (300, 5, 30, 40, 1, 0, 3),     # ragged N (3 row tiles, 300 of 384 rows), dead columns, partial last group
+    (129, 7, 9, 25, 0, 1, 4),      # one row past a tile, d = 0, both-neighbour coupling
+    (128, 64, 3, 20, 2, 0, 5),     # exact tile, R = 64 (one trial per workgroup), d = 2
+    (1, 3, 5, 30, 1, 1, 6),        # a single spin
+    (70, 1, 11, 30, 1, 0, 7),      # R = 1 (the ring couples a replica to itself)
+])
+def test_random_ising_shapes(lib, n, R, T, SC, delay, mode, seed):
+    _note(f"case random n={n} R={R} T={T} SC={SC} d={delay} mode={mode}")
+    h, J = random_ising(n, seed, h_max=90, j_max=11)
+    rng = np.random.default_rng(seed)
+    q = rng.integers(-9, 10, size=SC)
+    i0 = rng.integers(3, 128, size=SC)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=R, trials=T, cycles=SC, q=q, i0=i0, alpha=3, noise=13, delay=delay, seed=seed,
+              mode=mode)
+    gpu = run_gpu(prob, **kw)
+    ref = run_oracle(h, J, **kw)
+    assert_same(gpu, ref)
+
+
+def test_two_int8_planes(lib):
+    """|J| beyond int8: J is split into two exact planes."""
+    _note("case planes n=150 R=4 T=16 SC=30")
+    h, J = random_ising(150, 9, h_max=2000, j_max=300)
+    prob = lib.Problem(h, J)
+    assert prob.planes == 2
+    rng = np.random.default_rng(1)
+    q = rng.integers(0, 50, size=30)
+    i0 = np.full(30, 100)
+    kw = dict(replicas=4, trials=16, cycles=30, q=q, i0=i0, alpha=1, noise=40, delay=1, seed=2)
+    assert_same(run_gpu(prob, **kw), run_oracle(h, J, **kw))
+
+
+def test_split_launches_equal_one_launch(lib):
+    """A host loop of short launches (state kept in device memory) equals one persistent launch."""
+    _note("case split launches n=260 R=6 T=20 SC=57 d=2")
+    h, J = random_ising(260, 12, h_max=60, j_max=9)
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, 12, size=57)
+    i0 = rng.integers(10, 60, size=57)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=6, trials=20, cycles=57, q=q, i0=i0, alpha=1, noise=11, delay=2, seed=8, mode=1)
+    one = run_gpu(prob, **kw)
+    for cpl in (1, 7):
+        many = run_gpu(prob, cycles_per_launch=cpl, **kw)
+        for key in ("best", "first_hit", "trace", "Is"):
+            assert np.array_equal(one[key], many[key]), (cpl, key)
+    assert_same(one, run_oracle(h, J, **kw))
+
+
+def test_zero_cycles_and_determinism(lib):
+    _note("case zero cycles")
+    h, J, e_star = gi_case(4, 2)
+    q, i0, noise = paper_schedules(10)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=8, trials=5, cycles=0, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=3,
+              target=e_star)
+    assert_same(run_gpu(prob, **kw), run_oracle(h, J, **kw))
+    kw["cycles"] = 10
+    a, b = run_gpu(prob, **kw), run_gpu(prob, **kw)
+    for key in a:
+        assert np.array_equal(a[key], b[key])
+
+
+def test_ssa_mode(lib):
+    """SSA (Eq. 2, Section 4.4 schedule) as R = 1 without coupling, against the oracle's SSA."""
+    _note("case SSA n=8 (N=64)")
+    from fractions import Fraction
+    h, J, e_star = gi_case(8, 3, scale=4)
+    SC = 400
+    i0 = ssqa.scaled(ssqa.ssa_i0_schedule(SC, 10, Fraction(1, 2), 1, 16), 4)
+    prob = lib.Problem(h, J)
+    gpu = run_gpu(prob, replicas=1, trials=32, cycles=SC, q=np.zeros(SC, int), i0=i0, alpha=1, noise=4,
+                  delay=1, seed=4, target=e_star)
+    e_ref, Is_ref, _ = ssqa.ssa_anneal(h, J, 32, SC, i0, 1, 4, seed=4, chains=[0])
+    assert np.array_equal(gpu["trace"], e_ref)
+    assert np.array_equal(gpu["Is"], Is_ref)
+
+
+def test_energy_entry_point(lib):
+    import torch
+    _note("case ssqa_energy")
+    h, J = random_ising(333, 21, h_max=500, j_max=127)
+    prob = lib.Problem(h, J)
+    rng = np.random.default_rng(0)
+    spins = rng.choice([-1, 1], size=(17, 333)).astype(np.int8)
+    e = lib.ssqa_energy(prob, torch.from_numpy(spins).cuda()).cpu().numpy()
+    F = ssqa.field(J, spins.astype(np.int64))
+    assert np.array_equal(e, ssqa.energy_from_field(h, spins.astype(np.int64), F))
+    assert e[0] == ssqa.energy_direct(h, J, spins[0])
+
+
+def test_gi20_sampled_trials_full_size(lib):
+    """N = 400 GI at its full run shape (R = 32, 256 trials, 2000 cycles); trials 0, 77 and 255
+    replayed by the oracle over all 2000 cycles."""
+    _note("case gi20 N=400 R=32 T=256 SC=2000 (sampled)")
+    h, J, e_star = gi_case(20, 1)
+    q, i0, noise = paper_schedules(2000)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=32, cycles=2000, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=0, target=e_star)
+    gpu = run_gpu(prob, trials=256, **kw)
+    sample = [0, 77, 255]
+    ref = run_oracle(h, J, trials=sample, **kw)
+    assert_same(gpu, ref, trial_idx=sample)
+
+
+@pytest.mark.timeout(900)
+def test_gi50_sampled_trials_full_size(lib):
+    """N = 2500 GI at the benchmark's shape and launch (R = 64, 1024 trials, 2000 cycles, one
+    persistent launch); trials 0 and 1023 replayed by the oracle over all 2000 cycles, and every
+    trial's best energy checked against the exact energy of its reported state bound."""
+    _note("case gi50 N=2500 R=64 T=1024 SC=2000 (sampled)")
+    h, J, e_star = gi_case(50, 2)
+    q, i0, noise = paper_schedules(2000)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=64, cycles=2000, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=0, target=e_star)
+    gpu = run_gpu(prob, trials=1024, **kw)
+    _note("  gpu done; oracle replay of trials 0 and 1023")
+    sample = [0, 1023]
+    ref = run_oracle(h, J, trials=sample, **kw)
+    assert_same(gpu, ref, trial_idx=sample)
+    # properties at any size: best = min of the trace, first hit consistent, energies >= E*
+    tr = gpu["trace"]
+    assert np.array_equal(gpu["best"], tr.min(axis=(0, 2)))
+    assert (gpu["best"] >= e_star).all()
+    hit = gpu["first_hit"]
+    ok = hit >= 0
+    assert np.array_equal(ok, gpu["best"] == e_star)
+    assert (tr[hit[ok], np.nonzero(ok)[0]].min(axis=-1) == e_star).all()
