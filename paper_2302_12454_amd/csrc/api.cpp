@@ -20,8 +20,7 @@ struct ssqa_problem {
     int32_t device;
     DeviceProblem dev;
     int8_t* J_planes;
-    int32_t* h_pad;
-    int32_t* rowsum;
+    int32_t* rowvec;   // [h | h - rowsum | 2h - rowsum], np each
 };
 
 namespace {
@@ -125,13 +124,12 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     int32_t* h32 = nullptr;
     const size_t plane_bytes = (size_t)planes * np * np;
     hipError_t e = hipMalloc(&p->J_planes, plane_bytes);
-    if (e == hipSuccess) e = hipMalloc(&p->h_pad, (size_t)np * 4);
-    if (e == hipSuccess) e = hipMalloc(&p->rowsum, (size_t)np * 4);
+    if (e == hipSuccess) e = hipMalloc(&p->rowvec, (size_t)np * 4 * 3);
     if (e == hipSuccess) e = hipMalloc(&J32, (size_t)n * n * 4);
     if (e == hipSuccess) e = hipMalloc(&h32, (size_t)n * 4);
     if (e == hipSuccess) e = hipMemcpy(J32, J, (size_t)n * n * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h32, h, (size_t)n * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_prepare_planes(J32, h32, n, np, planes, p->J_planes, p->h_pad, p->rowsum, nullptr);
+    if (e == hipSuccess) e = launch_prepare_planes(J32, h32, n, np, planes, p->J_planes, p->rowvec, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (J32) (void)hipFree(J32);
     if (h32) (void)hipFree(h32);
@@ -144,8 +142,9 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     p->dev.np = np;
     p->dev.planes = planes;
     p->dev.J = p->J_planes;
-    p->dev.h = p->h_pad;
-    p->dev.rowsum = p->rowsum;
+    p->dev.h = p->rowvec;
+    p->dev.hr = p->rowvec + np;
+    p->dev.er = p->rowvec + 2 * np;
     *out = p;
     return SSQA_OK;
 }
@@ -154,8 +153,7 @@ void ssqa_destroy_problem(ssqa_problem_t p) {
     if (!p) return;
     DeviceGuard guard(p->device);
     if (p->J_planes) (void)hipFree(p->J_planes);
-    if (p->h_pad) (void)hipFree(p->h_pad);
-    if (p->rowsum) (void)hipFree(p->rowsum);
+    if (p->rowvec) (void)hipFree(p->rowvec);
     delete p;
 }
 

@@ -20,7 +20,8 @@ struct DeviceProblem {
     int32_t planes;     // P int8 planes, J = sum_p 256^p J_p
     const int8_t* J;    // [P][np][np] row-major, zero padded
     const int32_t* h;   // [np], zero padded
-    const int32_t* rowsum;  // [np]: sum_j J_ij
+    const int32_t* hr;  // [np]: h_i - sum_j J_ij   (field offset for x = (sigma + 1) / 2)
+    const int32_t* er;  // [np]: 2 h_i - sum_j J_ij (energy offset)
 };
 
 // Arguments of one launch of the persistent sweep kernel.
@@ -49,8 +50,9 @@ struct SweepArgs {
 };
 
 // Launchers (sweep.hip).  Return hipSuccess or the launch error.
+// rowvec receives [h | hr | er], three int32 vectors of np entries.
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
-                                 int8_t* Jp, int32_t* h_pad, int32_t* rowsum, hipStream_t stream);
+                                 int8_t* Jp, int32_t* rowvec, hipStream_t stream);
 int sweep_columns_per_wg();
 size_t sweep_lds_bytes(int np, int delay);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);

@@ -34,42 +34,62 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * 64;
 
-// Columns per workgroup.
-constexpr int kNBF = 4;              // 16-column MFMA fragments per workgroup
+// Columns per workgroup: 4 MFMA column fragments of 16.
+constexpr int kNBF = 4;
 constexpr int kNB = 16 * kNBF;
+static_assert(kNB == 64, "one Philox block per lane assumes 64 columns per workgroup");
 
 __device__ __forceinline__ int plane_stride(int np) { return np / 32 + 1; }
 
-// 16 bits (bit m = x for K offset m) -> 16 operand bytes 0/1 in K order.
-__device__ __forceinline__ v4i expand16(uint32_t v) {
-    v4i r;
-    r[0] = (int)((((v >> 0) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[1] = (int)((((v >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[2] = (int)((((v >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[3] = (int)((((v >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+// Bit-plane word layout.  Word w of a column holds spins 32 w .. 32 w + 31; spin offset
+// o = 16 h + 4 j + m (h < 2, j < 4, m < 4) sits at bit 8 m + 4 h + j.  With this spread order the
+// 16 MFMA operand bytes of a lane are (word >> (4 h + j)) & 0x01010101 for j = 0..3.
+__host__ __device__ constexpr int bitpos(int o) { return 8 * (o & 3) + 4 * (o >> 4) + ((o >> 2) & 3); }
+
+__device__ inline uint32_t spread_bits(uint32_t natural) {
+    uint32_t r = 0;
+    for (int o = 0; o < 32; ++o) r |= ((natural >> o) & 1u) << bitpos(o);
     return r;
 }
 
-__device__ __forceinline__ int sign_of_bit(uint32_t w, int m) { return ((w >> m) & 1u) ? 1 : -1; }
-
-__device__ __forceinline__ int8_t get_byte(const v4i& v, int m) { return (int8_t)((v[m >> 2] >> (8 * (m & 3))) & 0xFF); }
-
-__device__ __forceinline__ void put_byte(v4i& v, int m, int x) {
-    const int sh = 8 * (m & 3);
-    v[m >> 2] = (v[m >> 2] & ~(0xFF << sh)) | ((x & 0xFF) << sh);
+__device__ __forceinline__ v4i expand_operand(uint32_t w) {
+    // w already shifted by 4 h; bytes are x = (sigma + 1) / 2 in {0, 1}
+    v4i r;
+    r[0] = (int)(w & 0x01010101u);
+    r[1] = (int)((w >> 1) & 0x01010101u);
+    r[2] = (int)((w >> 2) & 0x01010101u);
+    r[3] = (int)((w >> 3) & 0x01010101u);
+    return r;
 }
 
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
+// 16 bytes of J at byte offset voffset + soffset of the plane buffer.
+__device__ __forceinline__ v4i load_j(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset) {
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voffset, soffset, 0);
+    return (v4i)x;
+}
+
+__device__ __forceinline__ int bfe_i(int w, int off, int width) { return __builtin_amdgcn_sbfe(w, off, width); }
+__device__ __forceinline__ uint32_t bfe_u(uint32_t w, int off, int width) { return __builtin_amdgcn_ubfe(w, off, width); }
+
+// LDS layout of one workgroup (dynamic shared memory, 32-bit words):
+//   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring)
+//   noise   [kWaves][64][4]             one Philox block per lane, exchanged inside the wave
+//   e_acc   [kNB]   int32               sum_i sigma_i (2 h_i + F_i) per column, this cycle
+//   hit     [kNB]   int32               per-trial first hit
+//   best    [kNB]   int64               per-trial best energy
+template <bool kAlpha1, int kMode>
+__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     extern __shared__ uint32_t lds[];
     const int np = a.prob.np;
-    const int n = a.prob.n;
     const int cstride = plane_stride(np);
     const int plane_words = kNB * cstride;
     const int npl = a.delay + 2;
     uint32_t* planes = lds;
-    int32_t* e_acc = reinterpret_cast<int32_t*>(lds + npl * plane_words);      // [kNB]
-    int32_t* hit_l = e_acc + kNB;                                               // [kNB]
-    long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);             // [kNB] (8-byte aligned)
+    uint32_t* noise_lds = lds + npl * plane_words;
+    int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * 64 * 4);
+    int32_t* hit_l = e_acc + kNB;
+    long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
 
     const int wg = blockIdx.x;
     const int tid = threadIdx.x;
@@ -101,15 +121,23 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
             const int b = b0 + c / R;
             const Philox4 x = philox4x32_10(0u, (uint32_t)tile, (uint32_t)k, (uint32_t)b, a.key0, a.key1);
             for (int w = 0; w < 4; ++w) {
+                const uint32_t sp = spread_bits(x.v[w]);
                 for (int s = 0; s <= a.delay; ++s) {
                     const int p = (npl - s) % npl;
-                    planes[p * plane_words + c * cstride + tile * 4 + w] = x.v[w];
+                    planes[p * plane_words + c * cstride + tile * 4 + w] = sp;
                 }
                 v4i* dst = reinterpret_cast<v4i*>(is_wg + (size_t)c * np + tile * kTileRows + 32 * w);
-                v4i lo = {0, 0, 0, 0}, hi = {0, 0, 0, 0};
-                for (int m = 0; m < 32; ++m) {
-                    const int val = ((x.v[w] >> m) & 1u) ? 0 : -a.alpha;
-                    if (m < 16) put_byte(lo, m, val); else put_byte(hi, m - 16, val);
+                v4i lo, hi;
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t d0 = 0, d1 = 0;
+                    for (int m = 0; m < 4; ++m) {
+                        const uint32_t v0 = ((x.v[w] >> (4 * q + m)) & 1u) ? 0u : (uint32_t)(-a.alpha) & 0xFFu;
+                        const uint32_t v1 = ((x.v[w] >> (16 + 4 * q + m)) & 1u) ? 0u : (uint32_t)(-a.alpha) & 0xFFu;
+                        d0 |= v0 << (8 * m);
+                        d1 |= v1 << (8 * m);
+                    }
+                    lo[q] = (int)d0;
+                    hi[q] = (int)d1;
                 }
                 dst[0] = lo;
                 dst[1] = hi;
@@ -124,9 +152,10 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
             const v4i* src = reinterpret_cast<const v4i*>(is_wg + (size_t)c * np + 32 * w);
             const v4i lo = src[0], hi = src[1];
             uint32_t bits = 0;
-            for (int m = 0; m < 32; ++m) {
-                const int8_t v = (m < 16) ? get_byte(lo, m) : get_byte(hi, m - 16);
-                bits |= (uint32_t)(v >= 0) << m;
+            for (int o = 0; o < 32; ++o) {
+                const int word = (o < 16) ? lo[(o >> 2) & 3] : hi[(o >> 2) & 3];
+                const int v = bfe_i(word, 8 * (o & 3), 8);
+                bits |= (uint32_t)(v >= 0) << bitpos(o);
             }
             planes[p_cur * plane_words + c * cstride + w] = bits;
             for (int s = 1; s <= a.delay; ++s) {
@@ -138,9 +167,14 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
     }
     __syncthreads();
 
-    const int32_t* __restrict__ hvec = a.prob.h;
-    const int32_t* __restrict__ rsum = a.prob.rowsum;
     const int P = a.prob.planes;
+    // Buffer resource over all J planes (gfx9 raw buffer, byte addressed).
+    const __amdgpu_buffer_rsrc_t jrsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(a.prob.J), 0, P * np * np, 0x00020000);
+    // This lane's column for the Philox block it computes each tile (the 64 lanes cover the 64 columns).
+    const int my_k = lane % R;
+    const int my_b = b0 + lane / R;
+    uint32_t* my_noise = noise_lds + (wave * 64 + lane) * 4;
 
     for (int t = a.t_begin; t <= a.t_end; ++t) {
         const bool update = t < a.t_end;
@@ -150,7 +184,13 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
         const int p_del = (t - a.delay + npl) % npl;
         const int q = update ? a.jperp[t] : 0;
         const int i0 = update ? a.i0[t] : 0;
+        const int two_n = 2 * a.noise_amp;
+        const int two_q = 2 * q;
+        // s = Is + 2 acc + (h - rowsum) - n_rnd - q (1 + mode) + 2 n_rnd [r = +1] + 2 q [sigma_up = +1] (+ dn)
+        const int adj = -a.noise_amp - q * (kMode == 1 ? 2 : 1);
         const uint32_t* pl_cur = planes + p_cur * plane_words;
+        const uint32_t* pl_del = planes + p_del * plane_words;
+        uint32_t* pl_next = planes + p_next * plane_words;
 
         for (int tile = wave; tile < ntiles; tile += kWaves) {
             v4i acc[8][kNBF];
@@ -159,8 +199,11 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
 #pragma unroll
                 for (int f = 0; f < kNBF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
 
-            // Row of J feeding output slot (ai, r = col16): tile row 32 (r / 4) + 4 ai + r % 4.
+            // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
+            // group g ends up with rows 32 g .. 32 g + 31.
             const int row_base = tile * kTileRows + 32 * (col16 >> 2) + (col16 & 3);
+            const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
+            const int bsh = 4 * (g & 1);
             for (int p = P - 1; p >= 0; --p) {
                 if (p < P - 1) {
 #pragma unroll
@@ -168,84 +211,111 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
 #pragma unroll
                         for (int f = 0; f < kNBF; ++f) acc[ai][f] = acc[ai][f] * 256;
                 }
-                const int8_t* Jp = a.prob.J + (size_t)p * np * np + (size_t)row_base * np + 16 * g;
+                // J is read through a buffer resource (loads past the planes return 0 instead of faulting).
+                // One A buffer: the loads of step s + 1 are issued right behind the MFMAs of step s that read
+                // the same registers, so their latency overlaps the rest of the MFMA pipeline.
+                const int voff = row_base * np + 16 * g;
+                const int plane_off = p * np * np;
+                v4i A[8];
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai) A[ai] = load_j(jrsrc, voff, plane_off + 4 * ai * np);
+                // Drain the first loads here: at the loop head the only loads in flight are then the ones the
+                // previous step issued in fragment order, and each MFMA group waits for its own fragment only.
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
                 for (int s = 0; s < nsteps; ++s) {
-                    v4i A[8];
-#pragma unroll
-                    for (int ai = 0; ai < 8; ++ai)
-                        A[ai] = *reinterpret_cast<const v4i*>(Jp + (size_t)(4 * ai) * np + s * kStepK);
                     v4i B[kNBF];
-                    const int wsel = 2 * s + (g >> 1);
-                    const int sh = 16 * (g & 1);
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) {
-                        const uint32_t w = pl_cur[(16 * f + col16) * cstride + wsel];
-                        B[f] = expand16((w >> sh) & 0xFFFFu);
-                    }
+                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bsrc[16 * f * cstride + 2 * s] >> bsh);
+                    // the last step re-reads its own operands instead of branching
+                    const int s_next = s + 1 < nsteps ? s + 1 : s;
 #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai)
+                    for (int ai = 0; ai < 8; ++ai) {
 #pragma unroll
                         for (int f = 0; f < kNBF; ++f)
                             acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], B[f], acc[ai][f], 0, 0, 0);
+                        A[ai] = load_j(jrsrc, voff, plane_off + 4 * ai * np + s_next * kStepK);
+                    }
                 }
             }
 
-            // Fused epilogue: lane (column 16 f + col16, group g) owns rows tile*128 + 32 g + 0..31.
+            // ---------------- fused epilogue ----------------
+            // Lane (column 16 f + col16, group g) owns tile rows 32 g .. 32 g + 31 of every fragment f.
             const int word = tile * 4 + g;
             const int row0 = tile * kTileRows + 32 * g;
+            if (update) {
+                // One Philox block per lane (column = lane), shared through LDS within the wave.
+                const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (uint32_t)my_k, (uint32_t)my_b,
+                                                a.key0, a.key1);
+                *reinterpret_cast<uint4*>(my_noise) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
 #pragma unroll
             for (int f = 0; f < kNBF; ++f) {
                 const int c = 16 * f + col16;
-                const int lb = c / R;
-                const int k = c - lb * R;
-                const int b = b0 + lb;
-                const bool valid = (c < a.cols_wg) && (b < a.T);
-                const uint32_t sig_w = pl_cur[c * cstride + word];
-                uint32_t up_w = 0, dn_w = 0, noise_w = 0;
+                const uint32_t nsig = ~pl_cur[c * cstride + word];
+                int ep = __builtin_popcount(nsig);
+                uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
                 v4i is_lo = {0, 0, 0, 0}, is_hi = {0, 0, 0, 0};
                 v4i* is_ptr = reinterpret_cast<v4i*>(is_wg + (size_t)c * np + row0);
                 if (update) {
-                    const int c_up = valid ? lb * R + (k + 1 == R ? 0 : k + 1) : c;
-                    const int c_dn = valid ? lb * R + (k == 0 ? R - 1 : k - 1) : c;
-                    up_w = planes[p_del * plane_words + c_up * cstride + word];
-                    dn_w = planes[p_del * plane_words + c_dn * cstride + word];
-                    noise_w = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (uint32_t)k, (uint32_t)b,
-                                            a.key0, a.key1).v[g];
+                    const int lb = c / R;
+                    const int k = c - lb * R;
+                    const bool real = c < a.cols_wg;
+                    const int c_up = real ? lb * R + (k + 1 == R ? 0 : k + 1) : c;
+                    up_w = pl_del[c_up * cstride + word];
+                    if (kMode == 1) {
+                        const int c_dn = real ? lb * R + (k == 0 ? R - 1 : k - 1) : c;
+                        dn_w = pl_del[c_dn * cstride + word];
+                    }
+                    noise_w = noise_lds[(wave * 64 + c) * 4 + g];
                     is_lo = is_ptr[0];
                     is_hi = is_ptr[1];
                 }
-                int epart = 0;
-                uint32_t new_w = 0;
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai) {
-                    const v4i h4 = *reinterpret_cast<const v4i*>(hvec + row0 + 4 * ai);
-                    const v4i r4 = *reinterpret_cast<const v4i*>(rsum + row0 + 4 * ai);
+                    const v4i er4 = *reinterpret_cast<const v4i*>(a.prob.er + row0 + 4 * ai);
+                    v4i hq4 = {0, 0, 0, 0};
+                    if (update) hq4 = *reinterpret_cast<const v4i*>(a.prob.hr + row0 + 4 * ai) + adj;
+                    const int isw = ai < 4 ? is_lo[ai] : is_hi[ai - 4];
+                    uint32_t isw_new = 0;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int m = 4 * ai + j;
-                        const int i = row0 + m;
-                        const int F = 2 * acc[ai][f][j] - r4[j];
-                        const int si = sign_of_bit(sig_w, m);
-                        if (i < n) epart += si * (2 * h4[j] + F);
+                        const int o = 4 * ai + j;
+                        const int pos = bitpos(o);
+                        const int a2 = acc[ai][f][j] << 1;
+                        // energy: sum_i sigma_i (2 h_i - rowsum_i + 2 acc_i); (e ^ -1) = -e - 1, and the -1s are
+                        // restored by the popcount of nsig taken above
+                        ep += (a2 + er4[j]) ^ bfe_i((int)nsig, pos, 1);
                         if (update) {
-                            int coupling = q * sign_of_bit(up_w, m);
-                            if (a.mode == 1) coupling += q * sign_of_bit(dn_w, m);
-                            const int isv = (m < 16) ? get_byte(is_lo, m) : get_byte(is_hi, m - 16);
-                            const int sum = isv + h4[j] + F + a.noise_amp * sign_of_bit(noise_w, m) + coupling;
-                            const int nv = sum >= i0 ? i0 - a.alpha : (sum < -i0 ? -i0 : sum);
-                            if (m < 16) put_byte(is_lo, m, nv); else put_byte(is_hi, m - 16, nv);
-                            new_w |= (uint32_t)(nv >= 0) << m;
+                            int s = a2 + hq4[j] + bfe_i(isw, 8 * j, 8);
+                            s += (int)bfe_u(noise_w, o, 1) * two_n;
+                            s += (int)bfe_u(up_w, pos, 1) * two_q;
+                            if (kMode == 1) s += (int)bfe_u(dn_w, pos, 1) * two_q;
+                            int nv;
+                            if (kAlpha1) {
+                                nv = min(max(s, -i0), i0 - 1);  // v_med3_i32
+                            } else {
+                                nv = s >= i0 ? i0 - a.alpha : (s < -i0 ? -i0 : s);
+                            }
+                            negbits |= ((uint32_t)nv >> 31) << pos;
+                            isw_new |= ((uint32_t)nv & 0xFFu) << (8 * j);
                         }
+                    }
+                    if (update) {
+                        if (ai < 4) is_lo[ai] = (int)isw_new; else is_hi[ai - 4] = (int)isw_new;
                     }
                 }
                 if (update) {
                     is_ptr[0] = is_lo;
                     is_ptr[1] = is_hi;
-                    planes[p_next * plane_words + c * cstride + word] = new_w;
+                    pl_next[c * cstride + word] = ~negbits;
                 }
-                epart += __shfl_xor(epart, 16);
-                epart += __shfl_xor(epart, 32);
-                if (g == 0 && valid) atomicAdd(&e_acc[c], epart);
+                ep += __shfl_xor(ep, 16);
+                ep += __shfl_xor(ep, 32);
+                const bool valid = (c < a.cols_wg) && (b0 + c / R < a.T);
+                if (g == 0 && valid) atomicAdd(&e_acc[c], ep);
             }
         }
         __syncthreads();
@@ -297,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
 // int32 J [n][n] -> P balanced int8 planes [P][np][np] (J = sum_p 256^p J_p), zero padded;
 // also the padded h and the row sums of J.
 __global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np,
-                                      int32_t P, int8_t* Jp, int32_t* h_pad, int32_t* rowsum) {
+                                      int32_t P, int8_t* Jp, int32_t* rowvec) {
     const int i = blockIdx.x;
     if (i >= np) return;
     long long rs = 0;
@@ -318,8 +388,11 @@ __global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, in
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        rowsum[i] = (int32_t)part[0];
-        h_pad[i] = i < n ? h32[i] : 0;
+        const int32_t rs = (int32_t)part[0];
+        const int32_t hv = i < n ? h32[i] : 0;
+        rowvec[i] = hv;
+        rowvec[np + i] = hv - rs;
+        rowvec[2 * np + i] = 2 * hv - rs;
     }
 }
 
@@ -367,27 +440,36 @@ int sweep_columns_per_wg() { return kNB; }
 
 size_t sweep_lds_bytes(int np, int delay) {
     const size_t plane_words = (size_t)kNB * (np / 32 + 1);
-    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kNB * 4 * 2 + (size_t)kNB * 8 + 8;
+    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)kNB * 4 * 2 + (size_t)kNB * 8;
 }
 
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
-                                 int8_t* Jp, int32_t* h_pad, int32_t* rowsum, hipStream_t stream) {
-    hipLaunchKernelGGL(prepare_planes_kernel, dim3(np), dim3(256), 0, stream, J32, h32, n, np, planes, Jp, h_pad,
-                       rowsum);
+                                 int8_t* Jp, int32_t* rowvec, hipStream_t stream) {
+    hipLaunchKernelGGL(prepare_planes_kernel, dim3(np), dim3(256), 0, stream, J32, h32, n, np, planes, Jp, rowvec);
+    return hipGetLastError();
+}
+
+template <bool kAlpha1, int kMode>
+hipError_t launch_sweep_variant(const SweepArgs& args, int n_wg, size_t lds, hipStream_t stream) {
+    static bool configured = false;
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    hipLaunchKernelGGL((sweep_kernel<kAlpha1, kMode>), dim3(n_wg), dim3(kThreads), lds, stream, args);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream) {
     const size_t lds = sweep_lds_bytes(args.prob.np, args.delay);
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        configured = true;
+    if (args.alpha == 1) {
+        return args.mode == 1 ? launch_sweep_variant<true, 1>(args, n_wg, lds, stream)
+                              : launch_sweep_variant<true, 0>(args, n_wg, lds, stream);
     }
-    hipLaunchKernelGGL(sweep_kernel, dim3(n_wg), dim3(kThreads), lds, stream, args);
-    return hipGetLastError();
+    return args.mode == 1 ? launch_sweep_variant<false, 1>(args, n_wg, lds, stream)
+                          : launch_sweep_variant<false, 0>(args, n_wg, lds, stream);
 }
 
 hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T, int32_t tpw,
