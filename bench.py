@@ -37,7 +37,21 @@ def parse():
     ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cycles", type=int, default=600)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain 1 GiB device-to-device copy: profiling it with FETCH_SIZE / WRITE_SIZE gives the factor
+    between those counters and real bytes."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": src.numel() * 4, "dispatches": 3}), flush=True)
 
 
 def cpu_baseline(h, J, e_star, wl, q, i0, sample_cycles):
@@ -64,6 +78,9 @@ def cpu_baseline(h, J, e_star, wl, q, i0, sample_cycles):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: trials and instances are independent and would be sharded "
               "across GPUs with no per-cycle exchange, but this build measures the single-GPU share.",

@@ -13,12 +13,26 @@ constexpr int kStepK = 64;
 // Largest delay d supported (bit-plane ring of d + 2 planes in LDS).
 constexpr int kMaxDelay = 6;
 
+// Byte offset of J_ij inside one int8 plane of padded size np, in the fragment-tiled layout the sweep
+// kernel reads: for row tile r (128 rows), K step s (64 columns) and fragment ai, one contiguous 1 KiB
+// block holds the 16 x 64 operand of a v_mfma_i32_16x16x64_i8 in lane order (lane = 16 g + slot holds
+// row slot -> tile row 32 (slot / 4) + 4 ai + slot % 4, columns 64 s + 16 g .. + 15).
+__host__ __device__ inline size_t tiled_offset(int i, int j, int np) {
+    const int nsteps = np / kStepK;
+    const int r = i >> 7, o = i & 127;
+    const int slot = 4 * (o >> 5) + (o & 3);
+    const int ai = (o & 31) >> 2;
+    const int s = j >> 6, gk = (j & 63) >> 4, byte = j & 15;
+    const int lane = gk * 16 + slot;
+    return ((size_t)(r * nsteps + s) * 8 + ai) * 1024 + (size_t)lane * 16 + byte;
+}
+
 // Device-side description of one problem.
 struct DeviceProblem {
     int32_t n;          // spins N
     int32_t np;         // N padded to a multiple of kTileRows (rows and columns of every plane)
     int32_t planes;     // P int8 planes, J = sum_p 256^p J_p
-    const int8_t* J;    // [P][np][np] row-major, zero padded
+    const int8_t* J;    // [P][np * np] in the fragment-tiled layout of tiled_offset, zero padded
     const int32_t* h;   // [np], zero padded
     const int32_t* hr;  // [np]: h_i - sum_j J_ij   (field offset for x = (sigma + 1) / 2)
     const int32_t* er;  // [np]: 2 h_i - sum_j J_ij (energy offset)

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     const int wg = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps tile offsets scalar
     const int col16 = lane & 15;
     const int g = lane >> 4;
     const int ntiles = np / kTileRows;
@@ -201,7 +201,6 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
 
             // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
             // group g ends up with rows 32 g .. 32 g + 31.
-            const int row_base = tile * kTileRows + 32 * (col16 >> 2) + (col16 & 3);
             const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
             const int bsh = 4 * (g & 1);
             for (int p = P - 1; p >= 0; --p) {
@@ -211,29 +210,35 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
 #pragma unroll
                         for (int f = 0; f < kNBF; ++f) acc[ai][f] = acc[ai][f] * 256;
                 }
-                // J is read through a buffer resource (loads past the planes return 0 instead of faulting).
-                // One A buffer: the loads of step s + 1 are issued right behind the MFMAs of step s that read
-                // the same registers, so their latency overlaps the rest of the MFMA pipeline.
-                const int voff = row_base * np + 16 * g;
-                const int plane_off = p * np * np;
+                // J is read through a buffer resource (loads past the planes return 0 instead of faulting), one
+                // contiguous 1 KiB fragment per load.  One A buffer: the loads of step s + 1 are issued right
+                // behind the MFMAs of step s that read the same registers, so their latency overlaps the rest of
+                // the MFMA pipeline.
+                const int voff = lane * 16;
+                const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
                 v4i A[8];
 #pragma unroll
-                for (int ai = 0; ai < 8; ++ai) A[ai] = load_j(jrsrc, voff, plane_off + 4 * ai * np);
+                for (int ai = 0; ai < 8; ++ai) A[ai] = load_j(jrsrc, voff, tile_off + ai * 1024);
+                uint32_t bw[kNBF];
+#pragma unroll
+                for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
                 // Drain the first loads here: at the loop head the only loads in flight are then the ones the
                 // previous step issued in fragment order, and each MFMA group waits for its own fragment only.
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
                 for (int s = 0; s < nsteps; ++s) {
                     v4i B[kNBF];
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bsrc[16 * f * cstride + 2 * s] >> bsh);
+                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
                     // the last step re-reads its own operands instead of branching
                     const int s_next = s + 1 < nsteps ? s + 1 : s;
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s_next];
 #pragma unroll
                     for (int ai = 0; ai < 8; ++ai) {
 #pragma unroll
                         for (int f = 0; f < kNBF; ++f)
                             acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], B[f], acc[ai][f], 0, 0, 0);
-                        A[ai] = load_j(jrsrc, voff, plane_off + 4 * ai * np + s_next * kStepK);
+                        A[ai] = load_j(jrsrc, voff, tile_off + (s_next * 8 + ai) * 1024);
                     }
                 }
             }
@@ -270,8 +275,9 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
                         dn_w = pl_del[c_dn * cstride + word];
                     }
                     noise_w = noise_lds[(wave * 64 + c) * 4 + g];
-                    is_lo = is_ptr[0];
-                    is_hi = is_ptr[1];
+                    // counters are touched once per cycle: stream them past the cache that holds J
+                    is_lo = __builtin_nontemporal_load(is_ptr);
+                    is_hi = __builtin_nontemporal_load(is_ptr + 1);
                 }
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai) {
@@ -308,8 +314,8 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
                     }
                 }
                 if (update) {
-                    is_ptr[0] = is_lo;
-                    is_ptr[1] = is_hi;
+                    __builtin_nontemporal_store(is_lo, is_ptr);
+                    __builtin_nontemporal_store(is_hi, is_ptr + 1);
                     pl_next[c * cstride + word] = ~negbits;
                 }
                 ep += __shfl_xor(ep, 16);
@@ -374,9 +380,10 @@ __global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, in
     for (int j = threadIdx.x; j < np; j += blockDim.x) {
         int v = (i < n && j < n) ? J32[(size_t)i * n + j] : 0;
         rs += v;
+        const size_t off = tiled_offset(i, j, np);
         for (int p = 0; p < P; ++p) {
             const int8_t d = (int8_t)(v & 0xFF);
-            Jp[(size_t)p * np * np + (size_t)i * np + j] = d;
+            Jp[(size_t)p * np * np + off] = d;
             v = (v - d) >> 8;
         }
     }
@@ -417,9 +424,9 @@ __global__ void energy_kernel(DeviceProblem prob, const int8_t* spins, int32_t c
     for (int i = threadIdx.x; i < prob.n; i += blockDim.x) {
         long long F = 0;
         for (int p = prob.planes - 1; p >= 0; --p) {
-            const int8_t* row = prob.J + (size_t)p * prob.np * prob.np + (size_t)i * prob.np;
+            const int8_t* plane = prob.J + (size_t)p * prob.np * prob.np;
             long long acc = 0;
-            for (int j = 0; j < prob.n; ++j) acc += (int)row[j] * (int)s[j];
+            for (int j = 0; j < prob.n; ++j) acc += (int)plane[tiled_offset(i, j, prob.np)] * (int)s[j];
             F = F * 256 + acc;
         }
         part += (long long)s[i] * (2LL * prob.h[i] + F);
