@@ -60,6 +60,19 @@ struct DeviceGuard {
     }
 };
 
+// Keep freed stream-ordered allocations in the device's default pool instead of returning them to the
+// driver at every synchronisation, so repeated anneals reuse their state buffers.
+void retain_pool_memory(int device) {
+    static bool done[64] = {};
+    if (device < 0 || device >= 64 || done[device]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t threshold = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+    }
+    done[device] = true;
+}
+
 int planes_needed(int32_t v) {
     int p = 0;
     do {
@@ -191,6 +204,7 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     DeviceGuard guard(prob->device);
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    retain_pool_memory(prob->device);
     const int nb = sweep_columns_per_wg();
     const int tpw = nb / R;
     const int n_wg = (T + tpw - 1) / tpw;

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * 64 * 4);
     int32_t* hit_l = e_acc + kNB;
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
+    uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
 
     const int wg = blockIdx.x;
     const int tid = threadIdx.x;
@@ -104,7 +105,18 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     const int words = np / 32;
     int8_t* is_wg = a.is_state + (size_t)wg * kNB * np;
 
-    for (int c = tid; c < kNB; c += kThreads) e_acc[c] = 0;
+    for (int c = tid; c < kNB; c += kThreads) {
+        e_acc[c] = 0;
+        // column c = lb R + k: its ring neighbours k + 1 and k - 1 (mod R) and whether it is a real trial
+        const int lb = c / R;
+        const int k = c - lb * R;
+        const bool real = c < a.cols_wg;
+        const bool valid = real && (b0 + lb < a.T);
+        const int c_up = real ? lb * R + (k + 1 == R ? 0 : k + 1) : c;
+        const int c_dn = real ? lb * R + (k == 0 ? R - 1 : k - 1) : c;
+        colinfo[c] = (uint32_t)c_up | ((uint32_t)c_dn << 8) | ((uint32_t)k << 16) | ((uint32_t)(lb & 0x7F) << 24) |
+                     ((uint32_t)valid << 31);
+    }
     for (int lb = tid; lb < a.tpw; lb += kThreads) {
         const int b = b0 + lb;
         const bool fresh = (a.t_begin == 0);
@@ -171,10 +183,6 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     // Buffer resource over all J planes (gfx9 raw buffer, byte addressed).
     const __amdgpu_buffer_rsrc_t jrsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(a.prob.J), 0, P * np * np, 0x00020000);
-    // This lane's column for the Philox block it computes each tile (the 64 lanes cover the 64 columns).
-    const int my_k = lane % R;
-    const int my_b = b0 + lane / R;
-    uint32_t* my_noise = noise_lds + (wave * 64 + lane) * 4;
 
     for (int t = a.t_begin; t <= a.t_end; ++t) {
         const bool update = t < a.t_end;
@@ -216,65 +224,89 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
                 // the MFMA pipeline.
                 const int voff = lane * 16;
                 const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
-                v4i A[8];
+                // Two A buffers, loads issued two K steps ahead: buffer b holds step s while the loads of step
+                // s + 2 refill it right behind the MFMAs that read it.
+                v4i A0[8], A1[8];
 #pragma unroll
-                for (int ai = 0; ai < 8; ++ai) A[ai] = load_j(jrsrc, voff, tile_off + ai * 1024);
+                for (int ai = 0; ai < 8; ++ai) A0[ai] = load_j(jrsrc, voff, tile_off + ai * 1024);
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai) A1[ai] = load_j(jrsrc, voff, tile_off + (8 + ai) * 1024);
                 uint32_t bw[kNBF];
 #pragma unroll
                 for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
-                // Drain the first loads here: at the loop head the only loads in flight are then the ones the
-                // previous step issued in fragment order, and each MFMA group waits for its own fragment only.
+                // Drain the first loads here: at the loop head the loads in flight are then exactly the ones the
+                // previous steps issued in fragment order, so each MFMA group waits for its own fragment only.
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-                for (int s = 0; s < nsteps; ++s) {
-                    v4i B[kNBF];
+                for (int s = 0; s < nsteps; s += 2) {
+                    // step s from A0 (nsteps is even)
+                    {
+                        v4i B[kNBF];
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
-                    // the last step re-reads its own operands instead of branching
-                    const int s_next = s + 1 < nsteps ? s + 1 : s;
+                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s_next];
+                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * (s + 1)];
+                        const int s_ld = s + 2 < nsteps ? s + 2 : nsteps - 1;
 #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai) {
+                        for (int ai = 0; ai < 8; ++ai) {
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f)
-                            acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], B[f], acc[ai][f], 0, 0, 0);
-                        A[ai] = load_j(jrsrc, voff, tile_off + (s_next * 8 + ai) * 1024);
+                            for (int f = 0; f < kNBF; ++f)
+                                acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0[ai], B[f], acc[ai][f], 0, 0, 0);
+                            A0[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                        }
+                    }
+                    // step s + 1 from A1
+                    {
+                        v4i B[kNBF];
+#pragma unroll
+                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
+                        const int s_b = s + 2 < nsteps ? s + 2 : s + 1;
+#pragma unroll
+                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s_b];
+                        const int s_ld = s + 3 < nsteps ? s + 3 : nsteps - 1;
+#pragma unroll
+                        for (int ai = 0; ai < 8; ++ai) {
+#pragma unroll
+                            for (int f = 0; f < kNBF; ++f)
+                                acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[ai], B[f], acc[ai][f], 0, 0, 0);
+                            A1[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                        }
                     }
                 }
             }
 
             // ---------------- fused epilogue ----------------
-            // Lane (column 16 f + col16, group g) owns tile rows 32 g .. 32 g + 31 of every fragment f.
-            const int word = tile * 4 + g;
-            const int row0 = tile * kTileRows + 32 * g;
+            // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live
+            // (in registers) across the K loop.
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int ecol = ln & 15;
+            const int eg = ln >> 4;
+            // Lane (column 16 f + ecol, group eg) owns tile rows 32 eg .. 32 eg + 31 of every fragment f.
+            const int word = tile * 4 + eg;
+            const int row0 = tile * kTileRows + 32 * eg;
             if (update) {
                 // One Philox block per lane (column = lane), shared through LDS within the wave.
-                const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (uint32_t)my_k, (uint32_t)my_b,
-                                                a.key0, a.key1);
-                *reinterpret_cast<uint4*>(my_noise) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
+                const uint32_t mine = colinfo[ln];
+                const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
+                                                (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
+                *reinterpret_cast<uint4*>(noise_lds + (wave * 64 + ln) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
 #pragma unroll
             for (int f = 0; f < kNBF; ++f) {
-                const int c = 16 * f + col16;
+                const int c = 16 * f + ecol;
+                const uint32_t info = colinfo[c];
                 const uint32_t nsig = ~pl_cur[c * cstride + word];
                 int ep = __builtin_popcount(nsig);
                 uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
                 v4i is_lo = {0, 0, 0, 0}, is_hi = {0, 0, 0, 0};
                 v4i* is_ptr = reinterpret_cast<v4i*>(is_wg + (size_t)c * np + row0);
                 if (update) {
-                    const int lb = c / R;
-                    const int k = c - lb * R;
-                    const bool real = c < a.cols_wg;
-                    const int c_up = real ? lb * R + (k + 1 == R ? 0 : k + 1) : c;
-                    up_w = pl_del[c_up * cstride + word];
-                    if (kMode == 1) {
-                        const int c_dn = real ? lb * R + (k == 0 ? R - 1 : k - 1) : c;
-                        dn_w = pl_del[c_dn * cstride + word];
-                    }
-                    noise_w = noise_lds[(wave * 64 + c) * 4 + g];
+                    up_w = pl_del[(info & 0xFFu) * cstride + word];
+                    if (kMode == 1) dn_w = pl_del[((info >> 8) & 0xFFu) * cstride + word];
+                    noise_w = noise_lds[(wave * 64 + c) * 4 + eg];
                     // counters are touched once per cycle: stream them past the cache that holds J
                     is_lo = __builtin_nontemporal_load(is_ptr);
                     is_hi = __builtin_nontemporal_load(is_ptr + 1);
@@ -320,8 +352,7 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
                 }
                 ep += __shfl_xor(ep, 16);
                 ep += __shfl_xor(ep, 32);
-                const bool valid = (c < a.cols_wg) && (b0 + c / R < a.T);
-                if (g == 0 && valid) atomicAdd(&e_acc[c], ep);
+                if (eg == 0 && (info >> 31)) atomicAdd(&e_acc[c], ep);
             }
         }
         __syncthreads();
@@ -447,7 +478,8 @@ int sweep_columns_per_wg() { return kNB; }
 
 size_t sweep_lds_bytes(int np, int delay) {
     const size_t plane_words = (size_t)kNB * (np / 32 + 1);
-    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)kNB * 4 * 2 + (size_t)kNB * 8;
+    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)kNB * 4 * 2 + (size_t)kNB * 8 +
+           (size_t)kNB * 4;
 }
 
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
