@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-cycles", type=int, default=600)
+    ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()

@@ -72,6 +72,113 @@ __device__ __forceinline__ v4i load_j(__amdgpu_buffer_rsrc_t rsrc, int voffset, 
 __device__ __forceinline__ int bfe_i(int w, int off, int width) { return __builtin_amdgcn_sbfe(w, off, width); }
 __device__ __forceinline__ uint32_t bfe_u(uint32_t w, int off, int width) { return __builtin_amdgcn_ubfe(w, off, width); }
 
+struct EpilogueCtx {
+    const uint32_t* pl_cur;   // sigma(t) bit plane
+    const uint32_t* pl_del;   // sigma(t - d) bit plane
+    uint32_t* pl_next;        // sigma(t + 1) bit plane
+    const uint32_t* noise_lds;
+    const uint32_t* colinfo;
+    int32_t* e_acc;
+    int8_t* is_wg;
+    const int32_t* hr;
+    const int32_t* er;
+    int np, cstride, tile, wave, lane;
+    int adj, two_n, two_q, i0, alpha;
+};
+
+// v_perm_b32 selectors that put byte 0 of the second operand at byte j and keep the other bytes of the first.
+__host__ __device__ constexpr uint32_t insert_byte_sel(int j) {
+    uint32_t sel = 0;
+    for (int i = 0; i < 4; ++i) sel |= (uint32_t)(i == j ? 0 : 4 + i) << (8 * i);
+    return sel;
+}
+
+__device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// Fused epilogue of one 128-row tile for the kNBF column fragments of this wave.  Lane (column
+// 16 f + (lane & 15), group g = lane >> 4) owns tile rows 32 g .. 32 g + 31 of fragment f, i.e. one 32-bit
+// word of every bit plane and of the Philox block, and 32 consecutive int8 counters.  With kUpdate the
+// counters and the next bit plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the
+// current state is always accumulated.
+template <bool kUpdate, bool kAlpha1, int kMode>
+__device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const EpilogueCtx& x) {
+    // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live (in
+    // registers) across the K loop.
+    int ln = x.lane;
+    asm volatile("" : "+v"(ln));
+    const int ecol = ln & 15;
+    const int eg = ln >> 4;
+    const int word = x.tile * 4 + eg;
+    const int row0 = x.tile * kTileRows + 32 * eg;
+    const int lo = -x.i0, hi = x.i0 - 1;
+
+#pragma unroll
+    for (int f = 0; f < kNBF; ++f) {
+        const int c = 16 * f + ecol;
+        const uint32_t info = x.colinfo[c];
+        const uint32_t nsig = ~x.pl_cur[c * x.cstride + word];
+        int ep = __builtin_popcount(nsig);
+        uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
+        v4i is_lo, is_hi;
+        v4i* is_ptr = reinterpret_cast<v4i*>(x.is_wg + (size_t)c * x.np + row0);
+        if (kUpdate) {
+            up_w = x.pl_del[(info & 0xFFu) * x.cstride + word];
+            if (kMode == 1) dn_w = x.pl_del[((info >> 8) & 0xFFu) * x.cstride + word];
+            noise_w = x.noise_lds[(x.wave * 64 + c) * 4 + eg];
+            // counters are touched once per cycle: stream them past the cache that holds J
+            is_lo = __builtin_nontemporal_load(is_ptr);
+            is_hi = __builtin_nontemporal_load(is_ptr + 1);
+        }
+#pragma unroll
+        for (int ai = 0; ai < 8; ++ai) {
+            const v4i er4 = *reinterpret_cast<const v4i*>(x.er + row0 + 4 * ai);
+            v4i hq4;
+            if (kUpdate) hq4 = *reinterpret_cast<const v4i*>(x.hr + row0 + 4 * ai) + x.adj;
+            // bit position of row offset 4 ai + j is 8 j + cpos
+            const int cpos = 4 * (ai >> 2) + (ai & 3);
+            uint32_t isw_new = 0;
+            const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = 4 * ai + j;
+                const int pos = 8 * j + cpos;
+                const int accv = acc[ai][f][j];
+                // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
+                ep += ((accv << 1) + er4[j]) ^ bfe_i((int)nsig, pos, 1);
+                if (kUpdate) {
+                    int t = (bfe_i((int)noise_w, o, 1) & x.two_n) + (bfe_i((int)up_w, pos, 1) & x.two_q);
+                    if (kMode == 1) t += bfe_i((int)dn_w, pos, 1) & x.two_q;
+                    const int sv = (accv << 1) + hq4[j] + t + bfe_i(isw, 8 * j, 8);
+                    int nv;
+                    if (kAlpha1) {
+                        nv = med3_i32(sv, lo, hi);
+                    } else {
+                        nv = sv >= x.i0 ? x.i0 - x.alpha : (sv < lo ? lo : sv);
+                    }
+                    isw_new = __builtin_amdgcn_perm(isw_new, (uint32_t)nv, insert_byte_sel(j));
+                }
+            }
+            if (kUpdate) {
+                // sign bit of byte j (bit 8 j + 7) -> bit 8 j + cpos of the plane word
+                negbits |= (isw_new >> (7 - cpos)) & (0x01010101u << cpos);
+                if (ai < 4) is_lo[ai] = (int)isw_new; else is_hi[ai - 4] = (int)isw_new;
+            }
+        }
+        if (kUpdate) {
+            __builtin_nontemporal_store(is_lo, is_ptr);
+            __builtin_nontemporal_store(is_hi, is_ptr + 1);
+            x.pl_next[c * x.cstride + word] = ~negbits;
+        }
+        ep += __shfl_xor(ep, 16);
+        ep += __shfl_xor(ep, 32);
+        if (eg == 0 && (info >> 31)) atomicAdd(&x.e_acc[c], ep);
+    }
+}
+
 // LDS layout of one workgroup (dynamic shared memory, 32-bit words):
 //   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring)
 //   noise   [kWaves][64][4]             one Philox block per lane, exchanged inside the wave
@@ -275,84 +382,38 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
             }
 
             // ---------------- fused epilogue ----------------
-            // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live
-            // (in registers) across the K loop.
-            int ln = lane;
-            asm volatile("" : "+v"(ln));
-            const int ecol = ln & 15;
-            const int eg = ln >> 4;
-            // Lane (column 16 f + ecol, group eg) owns tile rows 32 eg .. 32 eg + 31 of every fragment f.
-            const int word = tile * 4 + eg;
-            const int row0 = tile * kTileRows + 32 * eg;
+            EpilogueCtx ctx;
+            ctx.pl_cur = pl_cur;
+            ctx.pl_del = pl_del;
+            ctx.pl_next = pl_next;
+            ctx.noise_lds = noise_lds;
+            ctx.colinfo = colinfo;
+            ctx.e_acc = e_acc;
+            ctx.is_wg = is_wg;
+            ctx.hr = a.prob.hr;
+            ctx.er = a.prob.er;
+            ctx.np = np;
+            ctx.cstride = cstride;
+            ctx.tile = tile;
+            ctx.wave = wave;
+            ctx.lane = lane;
+            ctx.adj = adj;
+            ctx.two_n = two_n;
+            ctx.two_q = two_q;
+            ctx.i0 = i0;
+            ctx.alpha = a.alpha;
             if (update) {
                 // One Philox block per lane (column = lane), shared through LDS within the wave.
-                const uint32_t mine = colinfo[ln];
+                const uint32_t mine = colinfo[lane];
                 const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
                                                 (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
-                *reinterpret_cast<uint4*>(noise_lds + (wave * 64 + ln) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
+                *reinterpret_cast<uint4*>(noise_lds + (wave * 64 + lane) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-#pragma unroll
-            for (int f = 0; f < kNBF; ++f) {
-                const int c = 16 * f + ecol;
-                const uint32_t info = colinfo[c];
-                const uint32_t nsig = ~pl_cur[c * cstride + word];
-                int ep = __builtin_popcount(nsig);
-                uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
-                v4i is_lo = {0, 0, 0, 0}, is_hi = {0, 0, 0, 0};
-                v4i* is_ptr = reinterpret_cast<v4i*>(is_wg + (size_t)c * np + row0);
-                if (update) {
-                    up_w = pl_del[(info & 0xFFu) * cstride + word];
-                    if (kMode == 1) dn_w = pl_del[((info >> 8) & 0xFFu) * cstride + word];
-                    noise_w = noise_lds[(wave * 64 + c) * 4 + eg];
-                    // counters are touched once per cycle: stream them past the cache that holds J
-                    is_lo = __builtin_nontemporal_load(is_ptr);
-                    is_hi = __builtin_nontemporal_load(is_ptr + 1);
-                }
-#pragma unroll
-                for (int ai = 0; ai < 8; ++ai) {
-                    const v4i er4 = *reinterpret_cast<const v4i*>(a.prob.er + row0 + 4 * ai);
-                    v4i hq4 = {0, 0, 0, 0};
-                    if (update) hq4 = *reinterpret_cast<const v4i*>(a.prob.hr + row0 + 4 * ai) + adj;
-                    const int isw = ai < 4 ? is_lo[ai] : is_hi[ai - 4];
-                    uint32_t isw_new = 0;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int o = 4 * ai + j;
-                        const int pos = bitpos(o);
-                        const int a2 = acc[ai][f][j] << 1;
-                        // energy: sum_i sigma_i (2 h_i - rowsum_i + 2 acc_i); (e ^ -1) = -e - 1, and the -1s are
-                        // restored by the popcount of nsig taken above
-                        ep += (a2 + er4[j]) ^ bfe_i((int)nsig, pos, 1);
-                        if (update) {
-                            int s = a2 + hq4[j] + bfe_i(isw, 8 * j, 8);
-                            s += (int)bfe_u(noise_w, o, 1) * two_n;
-                            s += (int)bfe_u(up_w, pos, 1) * two_q;
-                            if (kMode == 1) s += (int)bfe_u(dn_w, pos, 1) * two_q;
-                            int nv;
-                            if (kAlpha1) {
-                                nv = min(max(s, -i0), i0 - 1);  // v_med3_i32
-                            } else {
-                                nv = s >= i0 ? i0 - a.alpha : (s < -i0 ? -i0 : s);
-                            }
-                            negbits |= ((uint32_t)nv >> 31) << pos;
-                            isw_new |= ((uint32_t)nv & 0xFFu) << (8 * j);
-                        }
-                    }
-                    if (update) {
-                        if (ai < 4) is_lo[ai] = (int)isw_new; else is_hi[ai - 4] = (int)isw_new;
-                    }
-                }
-                if (update) {
-                    __builtin_nontemporal_store(is_lo, is_ptr);
-                    __builtin_nontemporal_store(is_hi, is_ptr + 1);
-                    pl_next[c * cstride + word] = ~negbits;
-                }
-                ep += __shfl_xor(ep, 16);
-                ep += __shfl_xor(ep, 32);
-                if (eg == 0 && (info >> 31)) atomicAdd(&e_acc[c], ep);
+                fused_epilogue<true, kAlpha1, kMode>(acc, ctx);
+            } else {
+                fused_epilogue<false, kAlpha1, kMode>(acc, ctx);
             }
         }
         __syncthreads();
