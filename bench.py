@@ -27,6 +27,24 @@ INT8_MFMA_PEAK = 5.0e15      # MI355X dense int8 MFMA, ops/s
 HBM_PEAK = 8.0e12            # bytes/s
 
 METRIC = "spin-updates/s and time-to-solution @99% success (N=2500 GI), batched vs plain"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_12454_amd", "csrc", "sweep.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_gi50_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+    or None when the kernel source changed since those counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def parse():
@@ -169,7 +187,7 @@ def main():
         "tts99_s_per_trial_amortised": tts(sec / T),
         "tts99_s_latency_form": tts(sec),
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / INT8_MFMA_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / INT8_MFMA_PEAK, "traffic": measured_traffic(),
                      "kernel": "sweep_kernel", "ops_per_launch": ops},
         "paper_context": {"ssqa_N2500": {"p_s": 0.41, "t_s": 46.4, "tts99_s": 405,
                                          "hardware": "MATLAB R2020b, AMD Ryzen 9 5950X", "R": 25, "SC": 1600,
