@@ -127,6 +127,36 @@ typedef struct ssqa_anneal_outputs {
 ssqa_status ssqa_anneal(ssqa_problem_t problem, const ssqa_anneal_params* params,
                         const ssqa_anneal_outputs* outputs, void* hip_stream);
 
+/* ------------------------------------------------------------------------------------------- */
+/* Batched form: many anneals of uneven size in one persistent launch, replayed from a HIP graph.*/
+/* ------------------------------------------------------------------------------------------- */
+
+typedef struct ssqa_batch* ssqa_batch_t;
+
+/*
+ * Prepare `count` anneals to run together: anneal i applies params[i] to problems[i] and writes
+ * outputs[i], with exactly the results ssqa_anneal would give for it alone (the random stream depends
+ * only on the seed and the spin, replica, trial and cycle indices).  All problems must live on one
+ * device; params[i].cycles_per_launch must be 0.  The library splits every anneal into blocks of whole
+ * trials, orders all blocks by decreasing cost (N padded squared times cycles) and records one persistent
+ * launch over that work list (one per distinct (alpha == 1, coupling mode) pair present) plus the optional
+ * final-counter copies in a HIP graph.  Schedules are copied; problems, params' host arrays and the
+ * output device buffers must stay valid until ssqa_batch_destroy.  Device state for all anneals is
+ * allocated here.  Errors as for ssqa_anneal (the first failing anneal is named in ssqa_last_error()).
+ */
+ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
+                              const ssqa_anneal_outputs* outputs, ssqa_batch_t* out);
+
+/* Run the prepared anneals (a graph launch, asynchronous on `stream`).  May be called repeatedly; each
+ * run starts every anneal from cycle 0 and overwrites its outputs.  Runs of one batch must not overlap. */
+ssqa_status ssqa_batch_run(ssqa_batch_t batch, void* hip_stream);
+
+/* Number of workgroups (column blocks) in the batch's work list. */
+int32_t ssqa_batch_blocks(ssqa_batch_t batch);
+
+/* Free the batch's graph and device state.  NULL is ignored.  No run may still be in flight. */
+void ssqa_batch_destroy(ssqa_batch_t batch);
+
 /*
  * Problem Hamiltonian (Eq. 1 / Eq. 5) of `cols` spin configurations, exactly:
  *   spins    : device int8 [cols * N], configuration c at c * N + i, entries +1 or -1.

@@ -9,9 +9,11 @@ loudly if it has not been built.
 from .api import (  # noqa: F401
     SSQA_NO_TARGET,
     AnnealResult,
+    Batch,
     Problem,
     SSQAError,
     ssqa_anneal,
+    ssqa_batch_create,
     ssqa_create_problem,
     ssqa_energy,
     ssqa_gi_to_ising,

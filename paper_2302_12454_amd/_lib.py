@@ -59,6 +59,11 @@ SIGNATURES = {
     "ssqa_gi_to_ising": (ctypes.c_int, [ctypes.c_int32, c_uint8_p, c_uint8_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, c_int32_p, c_int32_p, c_int64_p]),
     "ssqa_philox4x32_10": (None, [c_uint32_p, c_uint32_p, c_uint32_p]),
+    "ssqa_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(AnnealParams),
+                                         ctypes.POINTER(AnnealOutputs), ctypes.POINTER(ctypes.c_void_p)]),
+    "ssqa_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ssqa_batch_blocks": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ssqa_batch_destroy": (None, [ctypes.c_void_p]),
 }
 
 _lib = None

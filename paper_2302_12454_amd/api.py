@@ -100,28 +100,23 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
-                noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
-                trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, stream=None,
-                out: AnnealResult | None = None) -> AnnealResult:
-    """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
-    current stream).  ``out`` may carry preallocated outputs of the right shapes."""
+def _alloc_outputs(problem: Problem, trials: int, replicas: int, cycles: int, trace: bool, final_is: bool):
     import torch
-    lib = _lib.load()
     dev = torch.device("cuda", problem.device)
+    return AnnealResult(
+        best_energy=torch.empty(trials, dtype=torch.int64, device=dev),
+        first_hit=torch.empty(trials, dtype=torch.int32, device=dev),
+        energy_trace=(torch.empty((cycles + 1, trials, replicas), dtype=torch.int32, device=dev) if trace else None),
+        final_is=(torch.empty((trials, replicas, problem.n), dtype=torch.int8, device=dev) if final_is else None),
+    )
+
+
+def _params(*, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, seed, coupling_mode=0, target=None,
+            cycles_per_launch=0):
     jperp = _i32(jperp)
     i0 = _i32(i0)
     if len(jperp) < cycles or len(i0) < cycles:
         raise ValueError("schedules shorter than cycles")
-    if out is None:
-        out = AnnealResult(
-            best_energy=torch.empty(trials, dtype=torch.int64, device=dev),
-            first_hit=torch.empty(trials, dtype=torch.int32, device=dev),
-            energy_trace=(torch.empty((cycles + 1, trials, replicas), dtype=torch.int32, device=dev)
-                          if trace else None),
-            final_is=(torch.empty((trials, replicas, problem.n), dtype=torch.int8, device=dev)
-                      if final_is else None),
-        )
     p = _lib.AnnealParams()
     p.replicas, p.trials, p.cycles = int(replicas), int(trials), int(cycles)
     p.delay, p.alpha, p.noise_amp = int(delay), int(alpha), int(noise_amp)
@@ -130,14 +125,90 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
     p.i0 = _ptr(i0, ctypes.c_int32)
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.target_energy = SSQA_NO_TARGET if target is None else int(target)
+    return p, (jperp, i0)          # keep the arrays alive as long as the struct
+
+
+def _outputs(out: AnnealResult):
     o = _lib.AnnealOutputs()
     o.best_energy = out.best_energy.data_ptr()
     o.first_hit = out.first_hit.data_ptr()
     o.energy_trace = out.energy_trace.data_ptr() if out.energy_trace is not None else None
     o.final_is = out.final_is.data_ptr() if out.final_is is not None else None
+    return o
+
+
+def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
+                noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
+                trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, stream=None,
+                out: AnnealResult | None = None) -> AnnealResult:
+    """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
+    current stream).  ``out`` may carry preallocated outputs of the right shapes."""
+    lib = _lib.load()
+    if out is None:
+        out = _alloc_outputs(problem, trials, replicas, cycles, trace, final_is)
+    p, keep = _params(replicas=replicas, trials=trials, cycles=cycles, jperp=jperp, i0=i0, alpha=alpha,
+                      noise_amp=noise_amp, delay=delay, seed=seed, coupling_mode=coupling_mode, target=target,
+                      cycles_per_launch=cycles_per_launch)
+    o = _outputs(out)
     _check(lib.ssqa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
            "ssqa_anneal")
+    del keep
     return out
+
+
+class Batch:
+    """ssqa_batch_create / run / destroy: many anneals in one persistent launch replayed from a HIP graph.
+
+    ``jobs`` is a list of (problem, kwargs) where kwargs are ssqa_anneal's keyword arguments (replicas,
+    trials, cycles, jperp, i0, alpha, noise_amp, delay, seed, coupling_mode, target, trace, final_is).
+    """
+
+    def __init__(self, jobs):
+        lib = _lib.load()
+        n = len(jobs)
+        self.problems = [p for p, _ in jobs]
+        self.results = []
+        self._keep = []
+        params = (_lib.AnnealParams * n)()
+        outs = (_lib.AnnealOutputs * n)()
+        handles = (ctypes.c_void_p * n)()
+        for i, (prob, kw) in enumerate(jobs):
+            kw = dict(kw)
+            trace = kw.pop("trace", False)
+            final_is = kw.pop("final_is", False)
+            res = _alloc_outputs(prob, kw["trials"], kw["replicas"], kw["cycles"], trace, final_is)
+            p, keep = _params(**kw)
+            params[i] = p
+            outs[i] = _outputs(res)
+            handles[i] = prob.handle
+            self.results.append(res)
+            self._keep.append(keep)
+        handle = ctypes.c_void_p()
+        _check(lib.ssqa_batch_create(n, handles, params, outs, ctypes.byref(handle)), "ssqa_batch_create")
+        self._handle = handle
+
+    @property
+    def blocks(self) -> int:
+        return int(_lib.load().ssqa_batch_blocks(self._handle))
+
+    def run(self, stream=None):
+        _check(_lib.load().ssqa_batch_run(self._handle, _stream_handle(stream)), "ssqa_batch_run")
+        return self.results
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _lib.load().ssqa_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ssqa_batch_create(jobs) -> Batch:
+    return Batch(jobs)
 
 
 def ssqa_energy(problem: Problem, spins, stream=None):

@@ -83,7 +83,67 @@ int planes_needed(int32_t v) {
     return p;
 }
 
+ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out) {
+    const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
+    if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
+    if (R > sweep_columns_per_wg())
+        return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d", R, sweep_columns_per_wg());
+    if ((long long)T * R > (1LL << 28)) return fail(SSQA_EINVAL, "trials * replicas too large");
+    if (pa->delay < 0 || pa->delay > kMaxDelay) return fail(SSQA_EINVAL, "delay %d outside [0, %d]", pa->delay, kMaxDelay);
+    if (pa->alpha < 1) return fail(SSQA_EINVAL, "alpha must be >= 1");
+    if (pa->noise_amp < 0 || pa->noise_amp > (1 << 20)) return fail(SSQA_EINVAL, "noise_amp outside [0, 2^20]");
+    if (pa->coupling_mode != 0 && pa->coupling_mode != 1) return fail(SSQA_EINVAL, "coupling_mode must be 0 or 1");
+    if (pa->cycles_per_launch < 0) return fail(SSQA_EINVAL, "cycles_per_launch must be >= 0");
+    if (!out->best_energy || !out->first_hit) return fail(SSQA_EINVAL, "best_energy and first_hit are required");
+    if (SC > 0 && (!pa->jperp || !pa->i0)) return fail(SSQA_EINVAL, "schedules are required");
+    for (int t = 0; t < SC; ++t) {
+        if (pa->i0[t] < pa->alpha || pa->i0[t] > 127)
+            return fail(SSQA_EINVAL, "i0[%d] = %d outside [alpha, 127]", t, pa->i0[t]);
+        if (pa->jperp[t] < -(1 << 20) || pa->jperp[t] > (1 << 20))
+            return fail(SSQA_EINVAL, "jperp[%d] = %d outside [-2^20, 2^20]", t, pa->jperp[t]);
+    }
+    if (sweep_lds_bytes(prob->dev.np, pa->delay) > 160 * 1024)
+        return fail(SSQA_ENOTSUP, "N = %d with delay %d needs %zu bytes of LDS per workgroup (> 160 KiB)",
+                    prob->dev.n, pa->delay, sweep_lds_bytes(prob->dev.np, pa->delay));
+    return SSQA_OK;
+}
+
+SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
+                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist) {
+    SweepArgs a{};
+    const int tpw = sweep_columns_per_wg() / pa->replicas;
+    a.prob = prob->dev;
+    a.R = pa->replicas;
+    a.T = pa->trials;
+    a.tpw = tpw;
+    a.cols_wg = tpw * pa->replicas;
+    a.delay = pa->delay;
+    a.alpha = pa->alpha;
+    a.noise_amp = pa->noise_amp;
+    a.mode = pa->coupling_mode;
+    a.key0 = (uint32_t)(pa->seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(pa->seed >> 32);
+    a.target = pa->target_energy;
+    a.jperp = d_jperp;
+    a.i0 = d_i0;
+    a.is_state = is_state;
+    a.hist_state = hist;
+    a.best = out->best_energy;
+    a.first_hit = out->first_hit;
+    a.trace = out->energy_trace;
+    return a;
+}
+
 }  // namespace
+
+struct ssqa_batch {
+    int device = 0;
+    int blocks = 0;
+    void* mem = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -178,28 +238,9 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
                         void* hip_stream) {
     g_last_error.clear();
     if (!prob || !pa || !out) return fail(SSQA_EINVAL, "NULL problem, params or outputs");
+    const ssqa_status st = check_params(prob, pa, out);
+    if (st != SSQA_OK) return st;
     const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
-    if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
-    if (R > sweep_columns_per_wg())
-        return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d", R, sweep_columns_per_wg());
-    if ((long long)T * R > (1LL << 28)) return fail(SSQA_EINVAL, "trials * replicas too large");
-    if (pa->delay < 0 || pa->delay > kMaxDelay) return fail(SSQA_EINVAL, "delay %d outside [0, %d]", pa->delay, kMaxDelay);
-    if (pa->alpha < 1) return fail(SSQA_EINVAL, "alpha must be >= 1");
-    if (pa->noise_amp < 0 || pa->noise_amp > (1 << 20)) return fail(SSQA_EINVAL, "noise_amp outside [0, 2^20]");
-    if (pa->coupling_mode != 0 && pa->coupling_mode != 1) return fail(SSQA_EINVAL, "coupling_mode must be 0 or 1");
-    if (pa->cycles_per_launch < 0) return fail(SSQA_EINVAL, "cycles_per_launch must be >= 0");
-    if (!out->best_energy || !out->first_hit) return fail(SSQA_EINVAL, "best_energy and first_hit are required");
-    if (SC > 0 && (!pa->jperp || !pa->i0)) return fail(SSQA_EINVAL, "schedules are required");
-    for (int t = 0; t < SC; ++t) {
-        if (pa->i0[t] < pa->alpha || pa->i0[t] > 127)
-            return fail(SSQA_EINVAL, "i0[%d] = %d outside [alpha, 127]", t, pa->i0[t]);
-        if (pa->jperp[t] < -(1 << 20) || pa->jperp[t] > (1 << 20))
-            return fail(SSQA_EINVAL, "jperp[%d] = %d outside [-2^20, 2^20]", t, pa->jperp[t]);
-    }
-
-    if (sweep_lds_bytes(prob->dev.np, pa->delay) > 160 * 1024)
-        return fail(SSQA_ENOTSUP, "N = %d with delay %d needs %zu bytes of LDS per workgroup (> 160 KiB)",
-                    prob->dev.n, pa->delay, sweep_lds_bytes(prob->dev.np, pa->delay));
 
     DeviceGuard guard(prob->device);
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
@@ -226,26 +267,7 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host schedules may be freed on return
 
     if (e == hipSuccess) {
-        SweepArgs a{};
-        a.prob = prob->dev;
-        a.R = R;
-        a.T = T;
-        a.tpw = tpw;
-        a.cols_wg = tpw * R;
-        a.delay = pa->delay;
-        a.alpha = pa->alpha;
-        a.noise_amp = pa->noise_amp;
-        a.mode = pa->coupling_mode;
-        a.key0 = (uint32_t)(pa->seed & 0xFFFFFFFFu);
-        a.key1 = (uint32_t)(pa->seed >> 32);
-        a.target = pa->target_energy;
-        a.jperp = d_jperp;
-        a.i0 = d_i0;
-        a.is_state = is_state;
-        a.hist_state = hist;
-        a.best = out->best_energy;
-        a.first_hit = out->first_hit;
-        a.trace = out->energy_trace;
+        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist);
         const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(SC, 1);
         int t = 0;
         do {
@@ -266,6 +288,159 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
         return e == hipErrorOutOfMemory ? fail(SSQA_ENOMEM, "device allocation failed") : hip_fail(e, "anneal");
     }
     return SSQA_OK;
+}
+
+ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
+                              const ssqa_anneal_outputs* outputs, ssqa_batch_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(SSQA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > 65535) return fail(SSQA_EINVAL, "count = %d outside [1, 65535]", count);
+    if (!problems || !params || !outputs) return fail(SSQA_EINVAL, "NULL problems, params or outputs");
+    const int nb = sweep_columns_per_wg();
+    const int device = problems[0] ? problems[0]->device : -1;
+    // sizes and validation
+    size_t sched_words = 0, is_bytes = 0;
+    std::vector<int> n_wg(count), tpw(count);
+    for (int i = 0; i < count; ++i) {
+        const ssqa_problem* p = problems[i];
+        if (!p) return fail(SSQA_EINVAL, "problems[%d] is NULL", i);
+        if (p->device != device) return fail(SSQA_EINVAL, "problems[%d] is on another device", i);
+        const ssqa_status st = check_params(p, &params[i], &outputs[i]);
+        if (st != SSQA_OK) {
+            const std::string msg = g_last_error;
+            return fail(st, "anneal %d: %s", i, msg.c_str());
+        }
+        if (params[i].cycles_per_launch != 0) return fail(SSQA_EINVAL, "anneal %d: cycles_per_launch must be 0", i);
+        tpw[i] = nb / params[i].replicas;
+        n_wg[i] = (params[i].trials + tpw[i] - 1) / tpw[i];
+        if (n_wg[i] > 65535) return fail(SSQA_ENOTSUP, "anneal %d needs more than 65535 blocks", i);
+        sched_words += 2 * (size_t)std::max(params[i].cycles, 1);
+        is_bytes += (size_t)n_wg[i] * nb * p->dev.np;
+    }
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
+
+    auto* b = new (std::nothrow) ssqa_batch();
+    if (!b) return fail(SSQA_ENOMEM, "host allocation failed");
+    b->device = device;
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t total_work = 0;
+    for (int i = 0; i < count; ++i) total_work += n_wg[i];
+    const size_t off_items = 0;
+    const size_t off_work = align(off_items + sizeof(SweepArgs) * count);
+    const size_t off_sched = align(off_work + sizeof(uint32_t) * total_work);
+    const size_t off_is = align(off_sched + sizeof(int32_t) * sched_words);
+    const size_t bytes = align(off_is + is_bytes);
+    hipError_t e = hipMalloc(&b->mem, bytes);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(SSQA_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    char* base = static_cast<char*>(b->mem);
+    auto* d_items = reinterpret_cast<SweepArgs*>(base + off_items);
+    auto* d_work = reinterpret_cast<uint32_t*>(base + off_work);
+    auto* d_sched = reinterpret_cast<int32_t*>(base + off_sched);
+    int8_t* d_is = reinterpret_cast<int8_t*>(base + off_is);
+
+    // host images of the argument blocks, the schedules and the work lists (one per kernel variant)
+    std::vector<SweepArgs> items(count);
+    std::vector<int32_t> sched(sched_words);
+    size_t so = 0, io = 0;
+    struct Entry {
+        double cost;
+        uint32_t code;
+    };
+    std::vector<Entry> lists[4];
+    int max_np[4] = {0, 0, 0, 0}, max_delay[4] = {0, 0, 0, 0};
+    for (int i = 0; i < count; ++i) {
+        const ssqa_anneal_params& pa = params[i];
+        const int SC = pa.cycles;
+        int32_t* jp = d_sched + so;
+        int32_t* i0 = d_sched + so + std::max(SC, 1);
+        if (SC > 0) {
+            std::memcpy(&sched[so], pa.jperp, (size_t)SC * 4);
+            std::memcpy(&sched[so + std::max(SC, 1)], pa.i0, (size_t)SC * 4);
+        }
+        so += 2 * (size_t)std::max(SC, 1);
+        items[i] = make_args(problems[i], &pa, &outputs[i], jp, i0, d_is + io, nullptr);
+        items[i].t_begin = 0;
+        items[i].t_end = SC;
+        items[i].final_pass = 1;
+        io += (size_t)n_wg[i] * nb * problems[i]->dev.np;
+        const int v = (pa.alpha == 1 ? 2 : 0) + pa.coupling_mode;
+        const double np = problems[i]->dev.np;
+        const double cost = np * np * problems[i]->dev.planes * (SC + 1.0);
+        for (int c = 0; c < n_wg[i]; ++c) lists[v].push_back({cost, ((uint32_t)i << 16) | (uint32_t)c});
+        max_np[v] = std::max(max_np[v], problems[i]->dev.np);
+        max_delay[v] = std::max(max_delay[v], pa.delay);
+    }
+    std::vector<uint32_t> work;
+    size_t list_off[4], list_len[4];
+    for (int v = 0; v < 4; ++v) {
+        std::stable_sort(lists[v].begin(), lists[v].end(), [](const Entry& x, const Entry& y) { return x.cost > y.cost; });
+        list_off[v] = work.size();
+        list_len[v] = lists[v].size();
+        for (const Entry& en : lists[v]) work.push_back(en.code);
+        if (list_len[v] && sweep_lds_bytes(max_np[v], max_delay[v]) > 160 * 1024) {
+            ssqa_batch_destroy(b);
+            return fail(SSQA_ENOTSUP, "batch needs more than 160 KiB of LDS per workgroup");
+        }
+    }
+    e = hipMemcpy(d_items, items.data(), sizeof(SweepArgs) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sched.empty())
+        e = hipMemcpy(d_sched, sched.data(), sizeof(int32_t) * sched.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = configure_sweep_kernels();
+    // record the launches once; every run replays them
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int v = 0; v < 4 && le == hipSuccess; ++v) {
+            if (!list_len[v]) continue;
+            le = launch_sweep_batch(d_items, d_work + list_off[v], (int)list_len[v], max_np[v], max_delay[v],
+                                    (v & 2) != 0, v & 1, b->capture);
+        }
+        for (int i = 0; i < count && le == hipSuccess; ++i) {
+            if (!outputs[i].final_is) continue;
+            le = launch_copy_final_is(items[i].is_state, problems[i]->dev.np, problems[i]->dev.n, params[i].replicas,
+                                      params[i].trials, tpw[i], outputs[i].final_is, b->capture);
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->capture, &g);
+        b->graph = g;
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        ssqa_batch_destroy(b);
+        return hip_fail(e, "batch_create");
+    }
+    b->blocks = (int)work.size();
+    *out = b;
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_batch_run(ssqa_batch_t b, void* hip_stream) {
+    g_last_error.clear();
+    if (!b) return fail(SSQA_EINVAL, "batch is NULL");
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
+    SSQA_HIP(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(hip_stream)), "batch_run");
+    return SSQA_OK;
+}
+
+int32_t ssqa_batch_blocks(ssqa_batch_t b) { return b ? b->blocks : 0; }
+
+void ssqa_batch_destroy(ssqa_batch_t b) {
+    if (!b) return;
+    DeviceGuard guard(b->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
 }
 
 ssqa_status ssqa_energy(ssqa_problem_t prob, const int8_t* spins, int32_t cols, int64_t* energies, void* hip_stream) {

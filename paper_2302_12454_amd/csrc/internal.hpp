@@ -68,8 +68,15 @@ struct SweepArgs {
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
                                  int8_t* Jp, int32_t* rowvec, hipStream_t stream);
 int sweep_columns_per_wg();
+// Sets the LDS limits of every sweep kernel variant once (before any launch or graph capture).
+hipError_t configure_sweep_kernels();
 size_t sweep_lds_bytes(int np, int delay);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
+// items: device array of anneals; work: device list of (item << 16 | column block), n_work entries.  The
+// LDS size is taken for the largest padded N and delay of the batch; all items share alpha == 1 or not
+// (alpha1) and the coupling mode.
+hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
+                              bool alpha1, int mode, hipStream_t stream);
 hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T,
                                 int32_t tpw, int8_t* out, hipStream_t stream);
 hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t cols, int64_t* energies,

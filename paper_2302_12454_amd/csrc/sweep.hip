@@ -185,8 +185,9 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const 
 //   e_acc   [kNB]   int32               sum_i sigma_i (2 h_i + F_i) per column, this cycle
 //   hit     [kNB]   int32               per-trial first hit
 //   best    [kNB]   int64               per-trial best energy
+// All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
 template <bool kAlpha1, int kMode>
-__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     extern __shared__ uint32_t lds[];
     const int np = a.prob.np;
     const int cstride = plane_stride(np);
@@ -199,7 +200,6 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
     uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
 
-    const int wg = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps tile offsets scalar
@@ -462,6 +462,21 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
     }
 }
 
+template <bool kAlpha1, int kMode>
+__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
+    sweep_block<kAlpha1, kMode>(a, blockIdx.x);
+}
+
+// Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
+// host in decreasing cost so that the largest blocks start first.
+template <bool kAlpha1, int kMode>
+__global__ __launch_bounds__(kThreads, 2) void sweep_batch_kernel(const SweepArgs* __restrict__ items,
+                                                                   const uint32_t* __restrict__ work) {
+    const uint32_t w = work[blockIdx.x];
+    const SweepArgs a = items[w >> 16];
+    sweep_block<kAlpha1, kMode>(a, (int)(w & 0xFFFFu));
+}
+
 // int32 J [n][n] -> P balanced int8 planes [P][np][np] (J = sum_p 256^p J_p), zero padded;
 // also the padded h and the row sums of J.
 __global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np,
@@ -551,18 +566,52 @@ hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t
 
 template <bool kAlpha1, int kMode>
 hipError_t launch_sweep_variant(const SweepArgs& args, int n_wg, size_t lds, hipStream_t stream) {
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
     hipLaunchKernelGGL((sweep_kernel<kAlpha1, kMode>), dim3(n_wg), dim3(kThreads), lds, stream, args);
     return hipGetLastError();
 }
 
+template <bool kAlpha1, int kMode>
+hipError_t configure_variant() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kAlpha1, kMode>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return e;
+}
+
+hipError_t configure_sweep_kernels() {
+    static hipError_t status = [] {
+        hipError_t e = configure_variant<true, 0>();
+        if (e == hipSuccess) e = configure_variant<true, 1>();
+        if (e == hipSuccess) e = configure_variant<false, 0>();
+        if (e == hipSuccess) e = configure_variant<false, 1>();
+        return e;
+    }();
+    return status;
+}
+
+template <bool kAlpha1, int kMode>
+hipError_t launch_batch_variant(const SweepArgs* items, const uint32_t* work, int n_work, size_t lds,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL((sweep_batch_kernel<kAlpha1, kMode>), dim3(n_work), dim3(kThreads), lds, stream, items, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
+                              bool alpha1, int mode, hipStream_t stream) {
+    const size_t lds = sweep_lds_bytes(max_np, max_delay);
+    if (alpha1) {
+        return mode == 1 ? launch_batch_variant<true, 1>(items, work, n_work, lds, stream)
+                         : launch_batch_variant<true, 0>(items, work, n_work, lds, stream);
+    }
+    return mode == 1 ? launch_batch_variant<false, 1>(items, work, n_work, lds, stream)
+                     : launch_batch_variant<false, 0>(items, work, n_work, lds, stream);
+}
+
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream) {
+    const hipError_t ce = configure_sweep_kernels();
+    if (ce != hipSuccess) return ce;
     const size_t lds = sweep_lds_bytes(args.prob.np, args.delay);
     if (args.alpha == 1) {
         return args.mode == 1 ? launch_sweep_variant<true, 1>(args, n_wg, lds, stream)
