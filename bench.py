@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50"])
+    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512"])
+    ap.add_argument("--batch-count", type=int, default=512, help="instances of the batch512 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -94,6 +95,79 @@ def cpu_baseline(h, J, e_star, wl, q, i0, sample_cycles):
                       f"{wl.spin_updates / (updates / dt):.0f} s)"}
 
 
+def batched_vs_plain(args):
+    """512 GI instances of uneven size (n ~ U{10..50}, p ~ U[0.3, 0.7], graph seed 1000 + g), R = 32,
+    T = 64, SC = 2000, the paper's schedule: one batched graph launch against one ssqa_anneal per
+    instance on the same stream (the plain form)."""
+    import numpy as np
+    import torch
+    import paper_2302_12454_amd as lib
+    from synth import WORKLOADS, uneven_gi_batch
+
+    base = WORKLOADS["gi50"]
+    R, T, SC = 32, 64, 2000
+    pairs = uneven_gi_batch(args.batch_count, 10, 50, 0.3, 0.7, seed_base=1000)
+    q = lib.ssqa_jperp_schedule(SC, base.tau, base.beta, 0, 1, 2, base.scale)
+    i0 = np.full(SC, int(base.i0 * base.scale), dtype=np.int32)
+    noise = int(base.n_rnd * base.scale)
+    jobs, e_stars, spins = [], [], []
+    for g, pair in enumerate(pairs):
+        h, J, e_star = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, base.scale)
+        prob = lib.Problem(h, J, device=0)
+        jobs.append((prob, dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=noise,
+                                delay=base.delay, seed=g, target=e_star)))
+        e_stars.append(e_star)
+        spins.append(len(h))
+    print(f"built {len(jobs)} problems", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    batch = lib.Batch(jobs)
+    batch.run(stream)
+    torch.cuda.synchronize()
+    print("batched warmup done", file=sys.stderr, flush=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    res = batch.run(stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    batched_ms = ev[0].elapsed_time(ev[1])
+    p_batched = [float((r.best_energy.cpu().numpy() == e).mean()) for r, e in zip(res, e_stars)]
+    print(f"batched {batched_ms:.1f} ms", file=sys.stderr, flush=True)
+    outs = [lib.ssqa_anneal(p, stream=stream, **kw) for p, kw in jobs[:4]]   # warm the plain path
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    outs = [lib.ssqa_anneal(p, stream=stream, **kw) for p, kw in jobs]
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev[2].elapsed_time(ev[3])
+    print(f"plain {plain_ms:.1f} ms", file=sys.stderr, flush=True)
+    same = all(np.array_equal(o.best_energy.cpu().numpy(), r.best_energy.cpu().numpy()) and
+               np.array_equal(o.first_hit.cpu().numpy(), r.first_hit.cpu().numpy()) for o, r in zip(outs, res))
+    updates = float(sum(spins)) * R * T * SC
+    ops = sum(2.0 * n * n * R * T * (SC + 1) for n in spins)
+    ps_min = min(p_batched)
+
+    def tts(t, p):
+        if p >= 1.0:
+            return t
+        if p <= 0.0:
+            return None
+        return t * math.log(0.01) / math.log(1.0 - p)
+
+    batch.close()
+    return {
+        "workload": f"batch{len(jobs)}: GI n ~ U{{10..50}}, p ~ U[0.3, 0.7], R={R}, T={T}, SC={SC}, tau={base.tau}",
+        "instances": len(jobs), "blocks": None, "spin_updates": updates,
+        "batched_ms": batched_ms, "plain_ms": plain_ms, "speedup": plain_ms / batched_ms,
+        "batched_spin_updates_per_s": updates / (batched_ms / 1e3),
+        "plain_spin_updates_per_s": updates / (plain_ms / 1e3),
+        "batched_int8_frac": ops / (batched_ms / 1e3) / INT8_MFMA_PEAK,
+        "p_s_mean": float(np.mean(p_batched)), "p_s_min": ps_min,
+        "tts99_all_instances_batched_s": tts(batched_ms / 1e3, ps_min),
+        "tts99_all_instances_plain_s": tts(plain_ms / 1e3, ps_min),
+        "plain_equals_batched": bool(same),
+    }
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -109,6 +183,9 @@ def main():
     import paper_2302_12454_amd as lib
     from synth import WORKLOADS, random_gi_pair
 
+    if args.workload == "batch512":
+        print(json.dumps({"metric": METRIC, "batched_vs_plain": batched_vs_plain(args)}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     pair = random_gi_pair(wl.n, wl.p, wl.graph_seed)
     h, J, e_star = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, wl.scale)

@@ -102,6 +102,9 @@ typedef struct ssqa_anneal_params {
     const int32_t* i0;         /* host int32 [cycles]: I_0(t), 1 <= alpha <= I_0(t) <= 127     */
     uint64_t seed;             /* Philox key                                                    */
     int64_t target_energy;     /* E* for first_hit, or SSQA_NO_TARGET                           */
+    int32_t block_columns;     /* columns (whole trials) per workgroup: 0 = automatic (64 when R <= 64
+                                  and the bit planes fit in LDS, else 32), or 32 / 64.  A tiling
+                                  choice only: results do not depend on it                        */
 } ssqa_anneal_params;
 
 typedef struct ssqa_anneal_outputs {
@@ -122,7 +125,8 @@ typedef struct ssqa_anneal_outputs {
  * The problem Hamiltonian H_p (Eq. 5) of every replica is evaluated at t = 0 .. SC (one extra field
  * pass after the last update) for best_energy, first_hit and the optional trace.
  * Asynchronous on `stream`; the host schedules are copied before return.  Requires
- * |J_perp(t)| <= 2^20 and n_rnd <= 2^20.  Returns SSQA_ENOTSUP for R > 64.
+ * |J_perp(t)| <= 2^20 and n_rnd <= 2^20.  Returns SSQA_ENOTSUP when R exceeds the columns per
+ * workgroup (64, or 32 for N above about 6500 with d = 1) or the bit planes do not fit in LDS.
  */
 ssqa_status ssqa_anneal(ssqa_problem_t problem, const ssqa_anneal_params* params,
                         const ssqa_anneal_outputs* outputs, void* hip_stream);

@@ -28,6 +28,7 @@ class AnnealParams(ctypes.Structure):
         ("i0", c_int32_p),
         ("seed", ctypes.c_uint64),
         ("target_energy", ctypes.c_int64),
+        ("block_columns", ctypes.c_int32),
     ]
 
 

@@ -112,7 +112,7 @@ def _alloc_outputs(problem: Problem, trials: int, replicas: int, cycles: int, tr
 
 
 def _params(*, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, seed, coupling_mode=0, target=None,
-            cycles_per_launch=0):
+            cycles_per_launch=0, block_columns=0):
     jperp = _i32(jperp)
     i0 = _i32(i0)
     if len(jperp) < cycles or len(i0) < cycles:
@@ -125,6 +125,7 @@ def _params(*, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, see
     p.i0 = _ptr(i0, ctypes.c_int32)
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.target_energy = SSQA_NO_TARGET if target is None else int(target)
+    p.block_columns = int(block_columns)
     return p, (jperp, i0)          # keep the arrays alive as long as the struct
 
 
@@ -139,8 +140,8 @@ def _outputs(out: AnnealResult):
 
 def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
                 noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
-                trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, stream=None,
-                out: AnnealResult | None = None) -> AnnealResult:
+                trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, block_columns: int = 0,
+                stream=None, out: AnnealResult | None = None) -> AnnealResult:
     """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
     current stream).  ``out`` may carry preallocated outputs of the right shapes."""
     lib = _lib.load()
@@ -148,7 +149,7 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
         out = _alloc_outputs(problem, trials, replicas, cycles, trace, final_is)
     p, keep = _params(replicas=replicas, trials=trials, cycles=cycles, jperp=jperp, i0=i0, alpha=alpha,
                       noise_amp=noise_amp, delay=delay, seed=seed, coupling_mode=coupling_mode, target=target,
-                      cycles_per_launch=cycles_per_launch)
+                      cycles_per_launch=cycles_per_launch, block_columns=block_columns)
     o = _outputs(out)
     _check(lib.ssqa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
            "ssqa_anneal")

@@ -83,11 +83,20 @@ int planes_needed(int32_t v) {
     return p;
 }
 
+// Columns per workgroup: the requested width, or 64 when R <= 64 and the bit planes fit in LDS, else 32.
+int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    if (pa->block_columns == 32 || pa->block_columns == 64) return pa->block_columns;
+    if (pa->replicas <= 64 && sweep_lds_bytes(prob->dev.np, pa->delay, 64) <= 160 * 1024) return 64;
+    return 32;
+}
+
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out) {
     const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
     if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
-    if (R > sweep_columns_per_wg())
-        return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d", R, sweep_columns_per_wg());
+    if (pa->block_columns != 0 && pa->block_columns != 32 && pa->block_columns != 64)
+        return fail(SSQA_EINVAL, "block_columns must be 0, 32 or 64");
+    const int nb = block_columns(prob, pa);
+    if (R > nb) return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d columns per workgroup", R, nb);
     if ((long long)T * R > (1LL << 28)) return fail(SSQA_EINVAL, "trials * replicas too large");
     if (pa->delay < 0 || pa->delay > kMaxDelay) return fail(SSQA_EINVAL, "delay %d outside [0, %d]", pa->delay, kMaxDelay);
     if (pa->alpha < 1) return fail(SSQA_EINVAL, "alpha must be >= 1");
@@ -102,17 +111,19 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
         if (pa->jperp[t] < -(1 << 20) || pa->jperp[t] > (1 << 20))
             return fail(SSQA_EINVAL, "jperp[%d] = %d outside [-2^20, 2^20]", t, pa->jperp[t]);
     }
-    if (sweep_lds_bytes(prob->dev.np, pa->delay) > 160 * 1024)
+    if (sweep_lds_bytes(prob->dev.np, pa->delay, nb) > 160 * 1024)
         return fail(SSQA_ENOTSUP, "N = %d with delay %d needs %zu bytes of LDS per workgroup (> 160 KiB)",
-                    prob->dev.n, pa->delay, sweep_lds_bytes(prob->dev.np, pa->delay));
+                    prob->dev.n, pa->delay, sweep_lds_bytes(prob->dev.np, pa->delay, nb));
     return SSQA_OK;
 }
 
 SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
                     const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist) {
     SweepArgs a{};
-    const int tpw = sweep_columns_per_wg() / pa->replicas;
+    const int nb = block_columns(prob, pa);
+    const int tpw = nb / pa->replicas;
     a.prob = prob->dev;
+    a.nb = nb;
     a.R = pa->replicas;
     a.T = pa->trials;
     a.tpw = tpw;
@@ -246,7 +257,7 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     retain_pool_memory(prob->device);
-    const int nb = sweep_columns_per_wg();
+    const int nb = block_columns(prob, pa);
     const int tpw = nb / R;
     const int n_wg = (T + tpw - 1) / tpw;
     const int np = prob->dev.np;
@@ -278,7 +289,7 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
             t = a.t_end;
         } while (e == hipSuccess && t < SC);
         if (e == hipSuccess && out->final_is)
-            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, out->final_is, stream);
+            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, out->final_is, stream);
     }
     if (is_state) (void)hipFreeAsync(is_state, stream);
     if (hist) (void)hipFreeAsync(hist, stream);
@@ -297,11 +308,10 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
     *out = nullptr;
     if (count < 1 || count > 65535) return fail(SSQA_EINVAL, "count = %d outside [1, 65535]", count);
     if (!problems || !params || !outputs) return fail(SSQA_EINVAL, "NULL problems, params or outputs");
-    const int nb = sweep_columns_per_wg();
     const int device = problems[0] ? problems[0]->device : -1;
     // sizes and validation
     size_t sched_words = 0, is_bytes = 0;
-    std::vector<int> n_wg(count), tpw(count);
+    std::vector<int> n_wg(count), tpw(count), nbs(count);
     for (int i = 0; i < count; ++i) {
         const ssqa_problem* p = problems[i];
         if (!p) return fail(SSQA_EINVAL, "problems[%d] is NULL", i);
@@ -312,11 +322,12 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
             return fail(st, "anneal %d: %s", i, msg.c_str());
         }
         if (params[i].cycles_per_launch != 0) return fail(SSQA_EINVAL, "anneal %d: cycles_per_launch must be 0", i);
-        tpw[i] = nb / params[i].replicas;
+        nbs[i] = block_columns(p, &params[i]);
+        tpw[i] = nbs[i] / params[i].replicas;
         n_wg[i] = (params[i].trials + tpw[i] - 1) / tpw[i];
         if (n_wg[i] > 65535) return fail(SSQA_ENOTSUP, "anneal %d needs more than 65535 blocks", i);
         sched_words += 2 * (size_t)std::max(params[i].cycles, 1);
-        is_bytes += (size_t)n_wg[i] * nb * p->dev.np;
+        is_bytes += (size_t)n_wg[i] * nbs[i] * p->dev.np;
     }
     DeviceGuard guard(device);
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
@@ -351,8 +362,9 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         double cost;
         uint32_t code;
     };
-    std::vector<Entry> lists[4];
-    int max_np[4] = {0, 0, 0, 0}, max_delay[4] = {0, 0, 0, 0};
+    constexpr int kVariants = 8;
+    std::vector<Entry> lists[kVariants];
+    int max_np[kVariants] = {}, max_delay[kVariants] = {};
     for (int i = 0; i < count; ++i) {
         const ssqa_anneal_params& pa = params[i];
         const int SC = pa.cycles;
@@ -367,8 +379,8 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         items[i].t_begin = 0;
         items[i].t_end = SC;
         items[i].final_pass = 1;
-        io += (size_t)n_wg[i] * nb * problems[i]->dev.np;
-        const int v = (pa.alpha == 1 ? 2 : 0) + pa.coupling_mode;
+        io += (size_t)n_wg[i] * nbs[i] * problems[i]->dev.np;
+        const int v = sweep_variant(pa.alpha == 1, pa.coupling_mode, nbs[i]);
         const double np = problems[i]->dev.np;
         const double cost = np * np * problems[i]->dev.planes * (SC + 1.0);
         for (int c = 0; c < n_wg[i]; ++c) lists[v].push_back({cost, ((uint32_t)i << 16) | (uint32_t)c});
@@ -376,13 +388,13 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         max_delay[v] = std::max(max_delay[v], pa.delay);
     }
     std::vector<uint32_t> work;
-    size_t list_off[4], list_len[4];
-    for (int v = 0; v < 4; ++v) {
+    size_t list_off[kVariants], list_len[kVariants];
+    for (int v = 0; v < kVariants; ++v) {
         std::stable_sort(lists[v].begin(), lists[v].end(), [](const Entry& x, const Entry& y) { return x.cost > y.cost; });
         list_off[v] = work.size();
         list_len[v] = lists[v].size();
         for (const Entry& en : lists[v]) work.push_back(en.code);
-        if (list_len[v] && sweep_lds_bytes(max_np[v], max_delay[v]) > 160 * 1024) {
+        if (list_len[v] && sweep_lds_bytes(max_np[v], max_delay[v], (v & 1) ? 32 : 64) > 160 * 1024) {
             ssqa_batch_destroy(b);
             return fail(SSQA_ENOTSUP, "batch needs more than 160 KiB of LDS per workgroup");
         }
@@ -397,15 +409,15 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
     if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
-        for (int v = 0; v < 4 && le == hipSuccess; ++v) {
+        for (int v = 0; v < kVariants && le == hipSuccess; ++v) {
             if (!list_len[v]) continue;
-            le = launch_sweep_batch(d_items, d_work + list_off[v], (int)list_len[v], max_np[v], max_delay[v],
-                                    (v & 2) != 0, v & 1, b->capture);
+            le = launch_sweep_batch(d_items, d_work + list_off[v], (int)list_len[v], max_np[v], max_delay[v], v,
+                                    b->capture);
         }
         for (int i = 0; i < count && le == hipSuccess; ++i) {
             if (!outputs[i].final_is) continue;
             le = launch_copy_final_is(items[i].is_state, problems[i]->dev.np, problems[i]->dev.n, params[i].replicas,
-                                      params[i].trials, tpw[i], outputs[i].final_is, b->capture);
+                                      params[i].trials, tpw[i], nbs[i], outputs[i].final_is, b->capture);
         }
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->capture, &g);

@@ -41,6 +41,7 @@ struct DeviceProblem {
 // Arguments of one launch of the persistent sweep kernel.
 struct SweepArgs {
     DeviceProblem prob;
+    int32_t nb;             // columns per workgroup: 64 or 32
     int32_t R;              // replicas
     int32_t T;              // trials
     int32_t tpw;            // trials per workgroup
@@ -56,8 +57,8 @@ struct SweepArgs {
     int64_t target;         // INT64_MIN for none
     const int32_t* jperp;   // device [cycles] indexed by absolute t
     const int32_t* i0;      // device [cycles]
-    int8_t* is_state;       // [n_wg * NB][np]: counters, column = wg * NB + local column
-    uint32_t* hist_state;   // [n_wg][delay][NB][np / 32]: sigma(t_begin - s) bits, s = 1..d
+    int8_t* is_state;       // [n_wg * nb][np]: counters, column = wg * nb + local column
+    uint32_t* hist_state;   // [n_wg][delay][nb][np / 32]: sigma(t_begin - s) bits, s = 1..d
     int64_t* best;          // [T]
     int32_t* first_hit;     // [T]
     int32_t* trace;         // [(SC + 1)][T * R] or nullptr; row t holds cycle t
@@ -67,18 +68,19 @@ struct SweepArgs {
 // rowvec receives [h | hr | er], three int32 vectors of np entries.
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
                                  int8_t* Jp, int32_t* rowvec, hipStream_t stream);
-int sweep_columns_per_wg();
 // Sets the LDS limits of every sweep kernel variant once (before any launch or graph capture).
 hipError_t configure_sweep_kernels();
-size_t sweep_lds_bytes(int np, int delay);
+// Dynamic LDS of one sweep workgroup for padded size np, delay d and nb columns.
+size_t sweep_lds_bytes(int np, int delay, int nb);
+// Kernel variant index of (alpha == 1, coupling mode, nb).
+int sweep_variant(bool alpha1, int mode, int nb);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
-// items: device array of anneals; work: device list of (item << 16 | column block), n_work entries.  The
-// LDS size is taken for the largest padded N and delay of the batch; all items share alpha == 1 or not
-// (alpha1) and the coupling mode.
+// items: device array of anneals; work: device list of (item << 16 | column block), n_work entries, all of
+// one kernel variant; the LDS size is taken for the largest padded N and delay among them.
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
-                              bool alpha1, int mode, hipStream_t stream);
+                              int variant, hipStream_t stream);
 hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T,
-                                int32_t tpw, int8_t* out, hipStream_t stream);
+                                int32_t tpw, int32_t nb, int8_t* out, hipStream_t stream);
 hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t cols, int64_t* energies,
                          hipStream_t stream);
 

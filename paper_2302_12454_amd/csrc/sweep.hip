@@ -34,10 +34,8 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * 64;
 
-// Columns per workgroup: 4 MFMA column fragments of 16.
-constexpr int kNBF = 4;
-constexpr int kNB = 16 * kNBF;
-static_assert(kNB == 64, "one Philox block per lane assumes 64 columns per workgroup");
+// Columns per workgroup: kNBF MFMA column fragments of 16 (kNBF = 4: 64 columns, the default; kNBF = 2:
+// 32 columns, for large N where the bit planes of 64 columns would not fit in LDS).
 
 __device__ __forceinline__ int plane_stride(int np) { return np / 32 + 1; }
 
@@ -104,7 +102,7 @@ __device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
 // word of every bit plane and of the Philox block, and 32 consecutive int8 counters.  With kUpdate the
 // counters and the next bit plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the
 // current state is always accumulated.
-template <bool kUpdate, bool kAlpha1, int kMode>
+template <bool kUpdate, bool kAlpha1, int kMode, int kNBF>
 __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const EpilogueCtx& x) {
     // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live (in
     // registers) across the K loop.
@@ -180,14 +178,16 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const 
 }
 
 // LDS layout of one workgroup (dynamic shared memory, 32-bit words):
-//   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring)
-//   noise   [kWaves][64][4]             one Philox block per lane, exchanged inside the wave
+//   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring), kNB = 16 kNBF columns
+//   noise   [kWaves][64][4]             one Philox block per column, exchanged inside the wave
 //   e_acc   [kNB]   int32               sum_i sigma_i (2 h_i + F_i) per column, this cycle
 //   hit     [kNB]   int32               per-trial first hit
 //   best    [kNB]   int64               per-trial best energy
+//   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
 // All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
-template <bool kAlpha1, int kMode>
+template <bool kAlpha1, int kMode, int kNBF>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
+    constexpr int kNB = 16 * kNBF;
     extern __shared__ uint32_t lds[];
     const int np = a.prob.np;
     const int cstride = plane_stride(np);
@@ -403,17 +403,21 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             ctx.i0 = i0;
             ctx.alpha = a.alpha;
             if (update) {
-                // One Philox block per lane (column = lane), shared through LDS within the wave.
-                const uint32_t mine = colinfo[lane];
-                const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
-                                                (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
-                *reinterpret_cast<uint4*>(noise_lds + (wave * 64 + lane) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
+                // One Philox block per column (lane c < kNB computes column c), shared through LDS within
+                // the wave.
+                if (kNB == 64 || lane < kNB) {
+                    const uint32_t mine = colinfo[lane];
+                    const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
+                                                    (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
+                    *reinterpret_cast<uint4*>(noise_lds + (wave * 64 + lane) * 4) =
+                        uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
+                }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                fused_epilogue<true, kAlpha1, kMode>(acc, ctx);
+                fused_epilogue<true, kAlpha1, kMode, kNBF>(acc, ctx);
             } else {
-                fused_epilogue<false, kAlpha1, kMode>(acc, ctx);
+                fused_epilogue<false, kAlpha1, kMode, kNBF>(acc, ctx);
             }
         }
         __syncthreads();
@@ -462,19 +466,19 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     }
 }
 
-template <bool kAlpha1, int kMode>
+template <bool kAlpha1, int kMode, int kNBF>
 __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
-    sweep_block<kAlpha1, kMode>(a, blockIdx.x);
+    sweep_block<kAlpha1, kMode, kNBF>(a, blockIdx.x);
 }
 
 // Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
 // host in decreasing cost so that the largest blocks start first.
-template <bool kAlpha1, int kMode>
+template <bool kAlpha1, int kMode, int kNBF>
 __global__ __launch_bounds__(kThreads, 2) void sweep_batch_kernel(const SweepArgs* __restrict__ items,
                                                                    const uint32_t* __restrict__ work) {
     const uint32_t w = work[blockIdx.x];
     const SweepArgs a = items[w >> 16];
-    sweep_block<kAlpha1, kMode>(a, (int)(w & 0xFFFFu));
+    sweep_block<kAlpha1, kMode, kNBF>(a, (int)(w & 0xFFFFu));
 }
 
 // int32 J [n][n] -> P balanced int8 planes [P][np][np] (J = sum_p 256^p J_p), zero padded;
@@ -511,14 +515,14 @@ __global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, in
 }
 
 __global__ void copy_final_is_kernel(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T,
-                                     int32_t tpw, int8_t* out) {
+                                     int32_t tpw, int32_t nb, int8_t* out) {
     const int col = blockIdx.x;   // b * R + k
     const int b = col / R;
     const int k = col - b * R;
     if (b >= T) return;
     const int wg = b / tpw;
     const int lc = (b - wg * tpw) * R + k;
-    const int8_t* src = is_state + ((size_t)wg * kNB + lc) * np;
+    const int8_t* src = is_state + ((size_t)wg * nb + lc) * np;
     for (int i = threadIdx.x; i < n; i += blockDim.x) out[(size_t)col * n + i] = src[i];
 }
 
@@ -550,12 +554,10 @@ __global__ void energy_kernel(DeviceProblem prob, const int8_t* spins, int32_t c
 
 }  // namespace
 
-int sweep_columns_per_wg() { return kNB; }
-
-size_t sweep_lds_bytes(int np, int delay) {
-    const size_t plane_words = (size_t)kNB * (np / 32 + 1);
-    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)kNB * 4 * 2 + (size_t)kNB * 8 +
-           (size_t)kNB * 4;
+size_t sweep_lds_bytes(int np, int delay, int nb) {
+    const size_t plane_words = (size_t)nb * (np / 32 + 1);
+    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)nb * 4 * 2 + (size_t)nb * 8 +
+           (size_t)nb * 4;
 }
 
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
@@ -564,66 +566,74 @@ hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t
     return hipGetLastError();
 }
 
-template <bool kAlpha1, int kMode>
-hipError_t launch_sweep_variant(const SweepArgs& args, int n_wg, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((sweep_kernel<kAlpha1, kMode>), dim3(n_wg), dim3(kThreads), lds, stream, args);
-    return hipGetLastError();
-}
-
-template <bool kAlpha1, int kMode>
+template <bool kAlpha1, int kMode, int kNBF>
 hipError_t configure_variant() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode, kNBF>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kAlpha1, kMode>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kAlpha1, kMode, kNBF>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     return e;
 }
 
 hipError_t configure_sweep_kernels() {
     static hipError_t status = [] {
-        hipError_t e = configure_variant<true, 0>();
-        if (e == hipSuccess) e = configure_variant<true, 1>();
-        if (e == hipSuccess) e = configure_variant<false, 0>();
-        if (e == hipSuccess) e = configure_variant<false, 1>();
+        hipError_t e = configure_variant<true, 0, 4>();
+        if (e == hipSuccess) e = configure_variant<true, 1, 4>();
+        if (e == hipSuccess) e = configure_variant<false, 0, 4>();
+        if (e == hipSuccess) e = configure_variant<false, 1, 4>();
+        if (e == hipSuccess) e = configure_variant<true, 0, 2>();
+        if (e == hipSuccess) e = configure_variant<true, 1, 2>();
+        if (e == hipSuccess) e = configure_variant<false, 0, 2>();
+        if (e == hipSuccess) e = configure_variant<false, 1, 2>();
         return e;
     }();
     return status;
 }
 
-template <bool kAlpha1, int kMode>
-hipError_t launch_batch_variant(const SweepArgs* items, const uint32_t* work, int n_work, size_t lds,
-                                hipStream_t stream) {
-    hipLaunchKernelGGL((sweep_batch_kernel<kAlpha1, kMode>), dim3(n_work), dim3(kThreads), lds, stream, items, work);
+int sweep_variant(bool alpha1, int mode, int nb) { return (alpha1 ? 4 : 0) + (mode ? 2 : 0) + (nb == 32 ? 1 : 0); }
+
+hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
+                              int variant, hipStream_t stream) {
+    const int nb = (variant & 1) ? 32 : 64;
+    const size_t lds = sweep_lds_bytes(max_np, max_delay, nb);
+    const dim3 grid(n_work), block(kThreads);
+    switch (variant) {
+        case 0: hipLaunchKernelGGL((sweep_batch_kernel<false, 0, 4>), grid, block, lds, stream, items, work); break;
+        case 1: hipLaunchKernelGGL((sweep_batch_kernel<false, 0, 2>), grid, block, lds, stream, items, work); break;
+        case 2: hipLaunchKernelGGL((sweep_batch_kernel<false, 1, 4>), grid, block, lds, stream, items, work); break;
+        case 3: hipLaunchKernelGGL((sweep_batch_kernel<false, 1, 2>), grid, block, lds, stream, items, work); break;
+        case 4: hipLaunchKernelGGL((sweep_batch_kernel<true, 0, 4>), grid, block, lds, stream, items, work); break;
+        case 5: hipLaunchKernelGGL((sweep_batch_kernel<true, 0, 2>), grid, block, lds, stream, items, work); break;
+        case 6: hipLaunchKernelGGL((sweep_batch_kernel<true, 1, 4>), grid, block, lds, stream, items, work); break;
+        case 7: hipLaunchKernelGGL((sweep_batch_kernel<true, 1, 2>), grid, block, lds, stream, items, work); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
-                              bool alpha1, int mode, hipStream_t stream) {
-    const size_t lds = sweep_lds_bytes(max_np, max_delay);
-    if (alpha1) {
-        return mode == 1 ? launch_batch_variant<true, 1>(items, work, n_work, lds, stream)
-                         : launch_batch_variant<true, 0>(items, work, n_work, lds, stream);
-    }
-    return mode == 1 ? launch_batch_variant<false, 1>(items, work, n_work, lds, stream)
-                     : launch_batch_variant<false, 0>(items, work, n_work, lds, stream);
-}
-
-hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream) {
+hipError_t launch_sweep(const SweepArgs& a, int n_wg, hipStream_t stream) {
     const hipError_t ce = configure_sweep_kernels();
     if (ce != hipSuccess) return ce;
-    const size_t lds = sweep_lds_bytes(args.prob.np, args.delay);
-    if (args.alpha == 1) {
-        return args.mode == 1 ? launch_sweep_variant<true, 1>(args, n_wg, lds, stream)
-                              : launch_sweep_variant<true, 0>(args, n_wg, lds, stream);
+    const size_t lds = sweep_lds_bytes(a.prob.np, a.delay, a.nb);
+    const dim3 grid(n_wg), block(kThreads);
+    switch (sweep_variant(a.alpha == 1, a.mode, a.nb)) {
+        case 0: hipLaunchKernelGGL((sweep_kernel<false, 0, 4>), grid, block, lds, stream, a); break;
+        case 1: hipLaunchKernelGGL((sweep_kernel<false, 0, 2>), grid, block, lds, stream, a); break;
+        case 2: hipLaunchKernelGGL((sweep_kernel<false, 1, 4>), grid, block, lds, stream, a); break;
+        case 3: hipLaunchKernelGGL((sweep_kernel<false, 1, 2>), grid, block, lds, stream, a); break;
+        case 4: hipLaunchKernelGGL((sweep_kernel<true, 0, 4>), grid, block, lds, stream, a); break;
+        case 5: hipLaunchKernelGGL((sweep_kernel<true, 0, 2>), grid, block, lds, stream, a); break;
+        case 6: hipLaunchKernelGGL((sweep_kernel<true, 1, 4>), grid, block, lds, stream, a); break;
+        case 7: hipLaunchKernelGGL((sweep_kernel<true, 1, 2>), grid, block, lds, stream, a); break;
+        default: return hipErrorInvalidValue;
     }
-    return args.mode == 1 ? launch_sweep_variant<false, 1>(args, n_wg, lds, stream)
-                          : launch_sweep_variant<false, 0>(args, n_wg, lds, stream);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T, int32_t tpw,
-                                int8_t* out, hipStream_t stream) {
-    hipLaunchKernelGGL(copy_final_is_kernel, dim3(T * R), dim3(256), 0, stream, is_state, np, n, R, T, tpw, out);
+                                int32_t nb, int8_t* out, hipStream_t stream) {
+    hipLaunchKernelGGL(copy_final_is_kernel, dim3(T * R), dim3(256), 0, stream, is_state, np, n, R, T, tpw, nb, out);
     return hipGetLastError();
 }
 

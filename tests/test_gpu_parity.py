@@ -172,3 +172,36 @@ def test_gi50_sampled_trials_full_size(lib):
     ok = hit >= 0
     assert np.array_equal(ok, gpu["best"] == e_star)
     assert (tr[hit[ok], np.nonzero(ok)[0]].min(axis=-1) == e_star).all()
+
+
+@pytest.mark.parametrize("n,R,T,SC,delay,mode", [(300, 5, 30, 40, 1, 0), (700, 32, 6, 30, 2, 1), (129, 1, 40, 25, 0, 0)])
+def test_block_width_invariance(lib, n, R, T, SC, delay, mode):
+    """The tiling choice (32 or 64 columns per workgroup) does not change any result."""
+    _note(f"case block width n={n} R={R} T={T}")
+    h, J = random_ising(n, n + R, h_max=70, j_max=8)
+    rng = np.random.default_rng(n)
+    q = rng.integers(0, 9, size=SC)
+    i0 = rng.integers(5, 100, size=SC)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=R, trials=T, cycles=SC, q=q, i0=i0, alpha=1, noise=10, delay=delay, seed=n, mode=mode)
+    wide = run_gpu(prob, block_columns=64, **kw)
+    narrow = run_gpu(prob, block_columns=32, **kw)
+    for key in ("best", "first_hit", "trace", "Is"):
+        assert np.array_equal(wide[key], narrow[key]), key
+    assert_same(narrow, run_oracle(h, J, **kw))
+
+
+def test_large_n_uses_narrow_blocks(lib):
+    """N = 6600 (padded 6656): 64-column bit planes exceed LDS, so 32-column blocks run; sampled trials
+    against the oracle."""
+    _note("case large N=6600 R=4 T=10 SC=12")
+    h, J = random_ising(6600, 77, h_max=40, j_max=3, density=0.3)
+    rng = np.random.default_rng(5)
+    SC = 12
+    q = rng.integers(0, 6, size=SC)
+    i0 = np.full(SC, 30)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=4, cycles=SC, q=q, i0=i0, alpha=1, noise=7, delay=1, seed=3)
+    gpu = run_gpu(prob, trials=10, **kw)
+    ref = run_oracle(h, J, trials=[0, 9], **kw)
+    assert_same(gpu, ref, trial_idx=[0, 9])
