@@ -161,6 +161,88 @@ int32_t ssqa_batch_blocks(ssqa_batch_t batch);
 /* Free the batch's graph and device state.  NULL is ignored.  No run may still be in flight. */
 void ssqa_batch_destroy(ssqa_batch_t batch);
 
+/* ------------------------------------------------------------------------------------------- */
+/* Serving: continuous batching of anneal requests with memory-based admission.                */
+/* ------------------------------------------------------------------------------------------- */
+
+typedef struct ssqa_server* ssqa_server_t;
+
+typedef struct ssqa_server_config {
+    int32_t device;            /* device every request runs on                                   */
+    int32_t cycles_per_step;   /* K >= 1: cycles every active request advances per step          */
+    int32_t max_active;        /* at most this many requests on the device at once (1..65535)    */
+    int64_t memory_budget;     /* bytes of device memory admitted requests may hold together     */
+} ssqa_server_config;
+
+typedef struct ssqa_request {
+    int32_t n_spins;           /* N, as for ssqa_create_problem                                   */
+    const int32_t* h;          /* host int32 [N], copied at submit                                */
+    const int32_t* J;          /* host int32 [N * N], symmetric, zero diagonal, copied at submit  */
+    ssqa_anneal_params params; /* as for ssqa_anneal; cycles = the most cycles the request may run;
+                                  schedules copied at submit; cycles_per_launch must be 0          */
+    int32_t early_exit;        /* 1: retire at the first step boundary where some trial's best
+                                  energy equals params.target_energy; 0: run all cycles           */
+} ssqa_request;
+
+typedef enum ssqa_request_state {
+    SSQA_REQ_QUEUED = 0,
+    SSQA_REQ_RUNNING = 1,
+    SSQA_REQ_DONE = 2,
+    SSQA_REQ_CANCELLED = 3,
+    SSQA_REQ_FAILED = 4        /* e.g. SSQA_ENOMEM: the request alone exceeds the memory budget   */
+} ssqa_request_state;
+
+typedef struct ssqa_request_info {
+    int32_t state;             /* ssqa_request_state                                              */
+    int32_t status;            /* ssqa_status of a failed request                                 */
+    int32_t cycles_done;       /* cycles the request has run                                      */
+    int32_t trials;
+    double submit_s, admit_s, done_s;  /* seconds since server creation (-1: not yet)            */
+    int64_t memory_bytes;      /* device memory charged to the request while it runs              */
+} ssqa_request_info;
+
+typedef struct ssqa_server_stats_t {
+    int32_t queued, active;
+    int64_t memory_in_use;
+    double spin_updates;       /* spin updates executed so far                                     */
+    double elapsed_s;          /* seconds since server creation                                    */
+} ssqa_server_stats_t;
+
+/*
+ * Create a request server (no device work until the first step).  The server is single-threaded:
+ * calls on one server must not overlap.
+ */
+ssqa_status ssqa_server_create(const ssqa_server_config* config, ssqa_server_t* out);
+
+/* Queue a request (first come, first served); `id` receives its handle. */
+ssqa_status ssqa_server_submit(ssqa_server_t server, const ssqa_request* request, int64_t* id);
+
+/*
+ * One serving step on `stream`: admit queued requests in order while the slot limit and the memory
+ * budget allow (a request that alone exceeds the budget fails with SSQA_ENOMEM), run K more cycles of
+ * every active request in one launch (each continues from its own cycle; counters, delayed spins and
+ * best energies stay on the device), read back the per-trial best energies and retire requests that
+ * finished their cycles or, with early_exit, reached their target.  Synchronises `stream`.
+ * `active` (may be NULL) receives the number of requests still running.  A request's results are the
+ * same alone or among others: best and first hit per trial equal those of ssqa_anneal with the same
+ * parameters (with early exit, best is the target for the trials that reached it by the retiring step).
+ */
+ssqa_status ssqa_server_step(ssqa_server_t server, void* hip_stream, int32_t* active);
+
+/* State and timings of a request; with `best` (host int64 [T]) and `first_hit` (host int32 [T]) non-NULL,
+ * also its per-trial results so far. */
+ssqa_status ssqa_server_poll(ssqa_server_t server, int64_t id, ssqa_request_info* info, int64_t* best,
+                             int32_t* first_hit);
+
+/* Cancel a queued or running request (a running one is released at the next step). */
+ssqa_status ssqa_server_cancel(ssqa_server_t server, int64_t id);
+
+/* Queue length, active requests, memory in use and work done so far. */
+ssqa_status ssqa_server_stats(ssqa_server_t server, ssqa_server_stats_t* stats);
+
+/* Release every request's device memory and the server.  NULL is ignored. */
+void ssqa_server_destroy(ssqa_server_t server);
+
 /*
  * Problem Hamiltonian (Eq. 1 / Eq. 5) of `cols` spin configurations, exactly:
  *   spins    : device int8 [cols * N], configuration c at c * N + i, entries +1 or -1.

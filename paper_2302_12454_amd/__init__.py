@@ -11,6 +11,7 @@ from .api import (  # noqa: F401
     AnnealResult,
     Batch,
     Problem,
+    Server,
     SSQAError,
     ssqa_anneal,
     ssqa_batch_create,
@@ -19,5 +20,6 @@ from .api import (  # noqa: F401
     ssqa_gi_to_ising,
     ssqa_jperp_schedule,
     ssqa_philox4x32_10,
+    ssqa_server_create,
     ssqa_ssa_i0_schedule,
 )

@@ -41,6 +41,48 @@ class AnnealOutputs(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("cycles_per_step", ctypes.c_int32),
+        ("max_active", ctypes.c_int32),
+        ("memory_budget", ctypes.c_int64),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("n_spins", ctypes.c_int32),
+        ("h", c_int32_p),
+        ("J", c_int32_p),
+        ("params", AnnealParams),
+        ("early_exit", ctypes.c_int32),
+    ]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("cycles_done", ctypes.c_int32),
+        ("trials", ctypes.c_int32),
+        ("submit_s", ctypes.c_double),
+        ("admit_s", ctypes.c_double),
+        ("done_s", ctypes.c_double),
+        ("memory_bytes", ctypes.c_int64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("queued", ctypes.c_int32),
+        ("active", ctypes.c_int32),
+        ("memory_in_use", ctypes.c_int64),
+        ("spin_updates", ctypes.c_double),
+        ("elapsed_s", ctypes.c_double),
+    ]
+
+
 # Every symbol include/ssqa.h declares, with (restype, argtypes).
 SIGNATURES = {
     "ssqa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -65,6 +107,14 @@ SIGNATURES = {
     "ssqa_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "ssqa_batch_blocks": (ctypes.c_int32, [ctypes.c_void_p]),
     "ssqa_batch_destroy": (None, [ctypes.c_void_p]),
+    "ssqa_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "ssqa_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), c_int64_p]),
+    "ssqa_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_int32_p]),
+    "ssqa_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(RequestInfo), c_int64_p,
+                                        c_int32_p]),
+    "ssqa_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "ssqa_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "ssqa_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 _lib = None

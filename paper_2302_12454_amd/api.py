@@ -262,3 +262,82 @@ def ssqa_philox4x32_10(ctr, key) -> list[int]:
     o = (ctypes.c_uint32 * 4)()
     _lib.load().ssqa_philox4x32_10(c, k, o)
     return [int(x) for x in o]
+
+
+REQUEST_STATES = {0: "queued", 1: "running", 2: "done", 3: "cancelled", 4: "failed"}
+
+
+class Server:
+    """ssqa_server_*: continuous batching of anneal requests with memory-based admission."""
+
+    def __init__(self, device: int = 0, cycles_per_step: int = 100, max_active: int = 64,
+                 memory_budget: int = 64 << 30):
+        lib = _lib.load()
+        cfg = _lib.ServerConfig(int(device), int(cycles_per_step), int(max_active), int(memory_budget))
+        handle = ctypes.c_void_p()
+        _check(lib.ssqa_server_create(ctypes.byref(cfg), ctypes.byref(handle)), "ssqa_server_create")
+        self._handle = handle
+        self._trials = {}
+
+    def submit(self, h, J, *, early_exit: bool = False, **anneal) -> int:
+        """Queue a request; ``anneal`` takes ssqa_anneal's parameters (replicas, trials, cycles, jperp, i0,
+        alpha, noise_amp, delay, seed, coupling_mode, target, block_columns)."""
+        lib = _lib.load()
+        h = _i32(h)
+        J = _i32(J)
+        n = int(h.shape[0])
+        if J.shape != (n, n):
+            raise ValueError(f"J must be {n} x {n}")
+        p, keep = _params(**anneal)
+        req = _lib.Request()
+        req.n_spins = n
+        req.h = _ptr(h, ctypes.c_int32)
+        req.J = _ptr(J, ctypes.c_int32)
+        req.params = p
+        req.early_exit = 1 if early_exit else 0
+        rid = ctypes.c_int64()
+        _check(lib.ssqa_server_submit(self._handle, ctypes.byref(req), ctypes.byref(rid)), "ssqa_server_submit")
+        del keep
+        self._trials[int(rid.value)] = int(anneal["trials"])
+        return int(rid.value)
+
+    def step(self, stream=None) -> int:
+        active = ctypes.c_int32()
+        _check(_lib.load().ssqa_server_step(self._handle, _stream_handle(stream), ctypes.byref(active)),
+               "ssqa_server_step")
+        return int(active.value)
+
+    def poll(self, rid: int) -> dict:
+        T = self._trials[rid]
+        info = _lib.RequestInfo()
+        best = np.zeros(T, dtype=np.int64)
+        hit = np.zeros(T, dtype=np.int32)
+        _check(_lib.load().ssqa_server_poll(self._handle, rid, ctypes.byref(info), _ptr(best, ctypes.c_int64),
+                                            _ptr(hit, ctypes.c_int32)), "ssqa_server_poll")
+        return {"state": REQUEST_STATES.get(info.state, str(info.state)), "status": int(info.status),
+                "cycles_done": int(info.cycles_done), "submit_s": info.submit_s, "admit_s": info.admit_s,
+                "done_s": info.done_s, "memory_bytes": int(info.memory_bytes), "best": best, "first_hit": hit}
+
+    def cancel(self, rid: int) -> None:
+        _check(_lib.load().ssqa_server_cancel(self._handle, rid), "ssqa_server_cancel")
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        _check(_lib.load().ssqa_server_stats(self._handle, ctypes.byref(st)), "ssqa_server_stats")
+        return {"queued": st.queued, "active": st.active, "memory_in_use": int(st.memory_in_use),
+                "spin_updates": st.spin_updates, "elapsed_s": st.elapsed_s}
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _lib.load().ssqa_server_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ssqa_server_create(**kw) -> Server:
+    return Server(**kw)

@@ -16,14 +16,8 @@
 
 using namespace ssqa;
 
-struct ssqa_problem {
-    int32_t device;
-    DeviceProblem dev;
-    int8_t* J_planes;
-    int32_t* rowvec;   // [h | h - rowsum | 2h - rowsum], np each
-};
-
-namespace {
+namespace ssqa {
+namespace detail {
 
 thread_local std::string g_last_error;
 
@@ -41,24 +35,14 @@ ssqa_status hip_fail(hipError_t e, const char* what) {
     return fail(SSQA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define SSQA_HIP(call, what)                          \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+DeviceGuard::DeviceGuard(int device) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(device) == hipSuccess;
+}
 
-// Device scope guard: makes `device` current and restores the previous device on exit.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int device) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(device) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+DeviceGuard::~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
 
 // Keep freed stream-ordered allocations in the device's default pool instead of returning them to the
 // driver at every synchronisation, so repeated anneals reuse their state buffers.
@@ -145,7 +129,10 @@ SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, cons
     return a;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace ssqa
+
+using namespace ssqa::detail;
 
 struct ssqa_batch {
     int device = 0;

@@ -85,3 +85,52 @@ hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t
                          hipStream_t stream);
 
 }  // namespace ssqa
+
+// ---------------------------------------------------------------------------------------------
+// Host-side pieces shared by the C ABI translation units (api.cpp, server.cpp).
+// ---------------------------------------------------------------------------------------------
+#include <string>
+
+#include "ssqa.h"
+
+struct ssqa_problem {
+    int32_t device;
+    ssqa::DeviceProblem dev;
+    int8_t* J_planes;
+    int32_t* rowvec;   // [h | h - rowsum | 2h - rowsum], np each
+};
+
+namespace ssqa {
+namespace detail {
+
+extern thread_local std::string g_last_error;
+// Record a formatted message for ssqa_last_error() and return `s`.
+ssqa_status fail(ssqa_status s, const char* fmt, ...);
+ssqa_status hip_fail(hipError_t e, const char* what);
+
+// Makes `device` current and restores the previous device on exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int device);
+    ~DeviceGuard();
+};
+
+// Columns per workgroup for an anneal of `prob` with `pa` (64 or 32).
+int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// Full argument check of one anneal; records the reason on failure.
+ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out);
+// Kernel arguments of one anneal (t_begin / t_end / final_pass left for the caller).
+SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
+                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist);
+// Keep freed stream-ordered allocations in the device pool.
+void retain_pool_memory(int device);
+
+}  // namespace detail
+}  // namespace ssqa
+
+#define SSQA_HIP(call, what)                                          \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return ssqa::detail::hip_fail(e_, what); \
+    } while (0)

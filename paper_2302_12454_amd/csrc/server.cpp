@@ -1,0 +1,393 @@
+// Serving: continuous batching of anneal requests (see include/ssqa.h, "Serving").
+//
+// Requests wait in a FIFO queue.  Every step admits requests from the head of the queue while the device
+// memory they need (problem planes + counters + bit-plane history + outputs) fits the budget and the slot
+// limit allows, then runs K cycles of every admitted request in one launch of the batch kernel (each
+// request continues from its own cycle; its counters and delayed bit planes stay in device memory between
+// steps), reads back the per-trial best energies, and retires requests that reached their target (early
+// exit) or their last cycle, releasing their memory.  A request's results depend only on its own inputs:
+// the random stream is keyed by its seed and its own cycle counter, and retirement is decided at its own
+// cycle boundaries, so a request gives the same result alone or among others.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace ssqa;
+using namespace ssqa::detail;
+
+namespace {
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct Request {
+    int64_t id = 0;
+    int32_t state = SSQA_REQ_QUEUED;
+    int32_t status = SSQA_OK;
+    int32_t early_exit = 0;
+    int n = 0;
+    int planes = 1;
+    std::vector<int32_t> h, J;           // host copies until admission
+    ssqa_anneal_params params{};
+    std::vector<int32_t> jperp, i0;
+    // device side, from admission to retirement
+    ssqa_problem_t prob = nullptr;
+    void* mem = nullptr;                 // schedules | counters | history | best | first_hit
+    int64_t bytes = 0;
+    int nb = 64, n_wg = 0;
+    SweepArgs args{};
+    int cycle = 0;
+    // results
+    std::vector<int64_t> best;
+    std::vector<int32_t> first_hit;
+    double submit_s = 0, admit_s = -1, done_s = -1;
+};
+
+int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa, int nb) {
+    const int64_t np = (n + kTileRows - 1) / kTileRows * kTileRows;
+    const int64_t tpw = nb / pa.replicas;
+    const int64_t n_wg = (pa.trials + tpw - 1) / tpw;
+    return planes_hint * np * np + 12 * np + n_wg * nb * np + n_wg * std::max(pa.delay, 1) * nb * np / 8 +
+           12LL * pa.trials + 8LL * std::max(pa.cycles, 1) + 1024;
+}
+
+}  // namespace
+
+struct ssqa_server {
+    ssqa_server_config cfg{};
+    std::chrono::steady_clock::time_point t0;
+    int64_t next_id = 1;
+    int64_t bytes_in_use = 0;
+    std::deque<Request*> queue;
+    std::vector<Request*> active;
+    std::map<int64_t, std::unique_ptr<Request>> all;
+    // per-step launch tables (device) and their host images
+    void* table = nullptr;
+    size_t table_bytes = 0;
+    std::vector<SweepArgs> items;
+    std::vector<uint32_t> work;
+    int64_t cycles_run = 0;
+    double spin_updates = 0;
+};
+
+namespace {
+
+void release_device(Request* r) {
+    if (r->mem) (void)hipFree(r->mem);
+    r->mem = nullptr;
+    if (r->prob) ssqa_destroy_problem(r->prob);
+    r->prob = nullptr;
+}
+
+// Upload the problem and allocate the request's state; returns SSQA_OK or the failure.
+ssqa_status admit(ssqa_server* s, Request* r) {
+    ssqa_status st = ssqa_create_problem(r->n, r->h.data(), r->J.data(), s->cfg.device, &r->prob);
+    if (st != SSQA_OK) return st;
+    ssqa_anneal_params& pa = r->params;
+    pa.jperp = r->jperp.data();
+    pa.i0 = r->i0.data();
+    const ssqa_anneal_outputs probe{reinterpret_cast<int64_t*>(1), reinterpret_cast<int32_t*>(1), nullptr, nullptr};
+    st = check_params(r->prob, &pa, &probe);
+    if (st != SSQA_OK) return st;
+    r->nb = block_columns(r->prob, &pa);
+    const int tpw = r->nb / pa.replicas;
+    r->n_wg = (pa.trials + tpw - 1) / tpw;
+    const int np = r->prob->dev.np;
+    const int SC = std::max(pa.cycles, 1);
+    const size_t o_sched = 0;
+    const size_t o_is = (size_t)(2 * SC * 4 + 255) / 256 * 256;
+    const size_t is_bytes = (size_t)r->n_wg * r->nb * np;
+    const size_t o_hist = o_is + (is_bytes + 255) / 256 * 256;
+    const size_t hist_bytes = (size_t)r->n_wg * std::max(pa.delay, 1) * r->nb * (np / 32) * 4;
+    const size_t o_best = o_hist + (hist_bytes + 255) / 256 * 256;
+    const size_t o_hit = o_best + ((size_t)pa.trials * 8 + 255) / 256 * 256;
+    const size_t total = o_hit + (size_t)pa.trials * 4;
+    DeviceGuard guard(s->cfg.device);
+    if (hipMalloc(&r->mem, total) != hipSuccess) return fail(SSQA_ENOMEM, "device allocation of %zu bytes failed", total);
+    char* base = static_cast<char*>(r->mem);
+    int32_t* d_jperp = reinterpret_cast<int32_t*>(base + o_sched);
+    int32_t* d_i0 = d_jperp + SC;
+    if (pa.cycles > 0) {
+        if (hipMemcpy(d_jperp, r->jperp.data(), (size_t)pa.cycles * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_i0, r->i0.data(), (size_t)pa.cycles * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(SSQA_EDEVICE, "schedule upload failed");
+    }
+    const ssqa_anneal_outputs outs{reinterpret_cast<int64_t*>(base + o_best), reinterpret_cast<int32_t*>(base + o_hit),
+                                   nullptr, nullptr};
+    r->args = make_args(r->prob, &pa, &outs, d_jperp, d_i0, reinterpret_cast<int8_t*>(base + o_is),
+                        reinterpret_cast<uint32_t*>(base + o_hist));
+    r->bytes = (int64_t)total + (int64_t)r->prob->dev.planes * np * np + 12LL * np;
+    r->cycle = 0;
+    r->best.assign(pa.trials, INT64_MAX);
+    r->first_hit.assign(pa.trials, -1);
+    // host copies of the problem are no longer needed
+    std::vector<int32_t>().swap(r->h);
+    std::vector<int32_t>().swap(r->J);
+    return SSQA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssqa_status ssqa_server_create(const ssqa_server_config* cfg, ssqa_server_t* out) {
+    g_last_error.clear();
+    if (!cfg || !out) return fail(SSQA_EINVAL, "NULL config or out");
+    *out = nullptr;
+    if (cfg->cycles_per_step < 1) return fail(SSQA_EINVAL, "cycles_per_step must be >= 1");
+    if (cfg->max_active < 1 || cfg->max_active > 65535) return fail(SSQA_EINVAL, "max_active outside [1, 65535]");
+    if (cfg->memory_budget < 1) return fail(SSQA_EINVAL, "memory_budget must be positive");
+    if (cfg->device < 0) return fail(SSQA_EINVAL, "device must be >= 0");
+    auto* s = new (std::nothrow) ssqa_server();
+    if (!s) return fail(SSQA_ENOMEM, "host allocation failed");
+    s->cfg = *cfg;
+    s->t0 = std::chrono::steady_clock::now();
+    *out = s;
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_server_submit(ssqa_server_t s, const ssqa_request* req, int64_t* id) {
+    g_last_error.clear();
+    if (!s || !req || !id) return fail(SSQA_EINVAL, "NULL argument");
+    const ssqa_anneal_params& pa = req->params;
+    if (req->n_spins < 1 || req->n_spins > 16384 || !req->h || !req->J)
+        return fail(SSQA_EINVAL, "bad problem (n_spins = %d)", req->n_spins);
+    if (pa.cycles < 0 || pa.replicas < 1 || pa.trials < 1 || (pa.cycles > 0 && (!pa.jperp || !pa.i0)))
+        return fail(SSQA_EINVAL, "bad anneal parameters");
+    if (pa.cycles_per_launch != 0) return fail(SSQA_EINVAL, "cycles_per_launch must be 0 for served requests");
+    if (req->early_exit != 0 && req->early_exit != 1) return fail(SSQA_EINVAL, "early_exit must be 0 or 1");
+    auto r = std::make_unique<Request>();
+    r->id = s->next_id++;
+    r->n = req->n_spins;
+    r->early_exit = req->early_exit;
+    r->h.assign(req->h, req->h + req->n_spins);
+    r->J.assign(req->J, req->J + (size_t)req->n_spins * req->n_spins);
+    r->params = pa;
+    r->jperp.assign(pa.jperp, pa.jperp + pa.cycles);
+    r->i0.assign(pa.i0, pa.i0 + pa.cycles);
+    // int8 planes needed by J (balanced base-256 digits), for the memory charge before admission
+    int planes = 1;
+    for (int32_t v : r->J) {
+        int p = 0;
+        do {
+            const int8_t d = (int8_t)(v & 0xFF);
+            v = (v - d) >> 8;
+            ++p;
+        } while (v != 0);
+        planes = std::max(planes, p);
+    }
+    r->planes = planes;
+    r->submit_s = now_s(s->t0);
+    s->queue.push_back(r.get());
+    *id = r->id;
+    s->all[r->id] = std::move(r);
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_out) {
+    g_last_error.clear();
+    if (!s) return fail(SSQA_EINVAL, "server is NULL");
+    DeviceGuard guard(s->cfg.device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice(%d) failed", s->cfg.device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+
+    // 1. admission, first come first served
+    while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
+        Request* r = s->queue.front();
+        if (r->state == SSQA_REQ_CANCELLED) {
+            s->queue.pop_front();
+            continue;
+        }
+        const int64_t need = request_bytes(r->n, r->planes, r->params, 32);
+        if (need > s->cfg.memory_budget) {          // can never fit: refuse it
+            s->queue.pop_front();
+            r->state = SSQA_REQ_FAILED;
+            r->status = SSQA_ENOMEM;
+            r->done_s = now_s(s->t0);
+            continue;
+        }
+        if (s->bytes_in_use + need > s->cfg.memory_budget) break;   // wait for memory to free up
+        s->queue.pop_front();
+        const ssqa_status st = admit(s, r);
+        if (st != SSQA_OK) {
+            release_device(r);
+            r->state = SSQA_REQ_FAILED;
+            r->status = st;
+            r->done_s = now_s(s->t0);
+            continue;
+        }
+        r->bytes = std::max(r->bytes, need);
+        s->bytes_in_use += r->bytes;
+        r->state = SSQA_REQ_RUNNING;
+        r->admit_s = now_s(s->t0);
+        s->active.push_back(r);
+    }
+    // drop cancelled requests
+    for (size_t i = 0; i < s->active.size();) {
+        Request* r = s->active[i];
+        if (r->state == SSQA_REQ_CANCELLED) {
+            release_device(r);
+            s->bytes_in_use -= r->bytes;
+            r->done_s = now_s(s->t0);
+            s->active.erase(s->active.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+    if (active_out) *active_out = (int32_t)s->active.size();
+    if (s->active.empty()) return SSQA_OK;
+
+    // 2. one launch per kernel variant over the blocks of every active request, K cycles each
+    const int K = s->cfg.cycles_per_step;
+    const int n = (int)s->active.size();
+    constexpr int kVariants = 8;
+    struct Entry {
+        double cost;
+        uint32_t code;
+    };
+    std::vector<Entry> lists[kVariants];
+    int max_np[kVariants] = {}, max_delay[kVariants] = {};
+    s->items.resize(n);
+    double updates = 0;
+    for (int i = 0; i < n; ++i) {
+        Request* r = s->active[i];
+        SweepArgs a = r->args;
+        a.t_begin = r->cycle;
+        a.t_end = std::min(r->params.cycles, r->cycle + K);
+        a.final_pass = a.t_end == r->params.cycles ? 1 : 0;
+        s->items[i] = a;
+        updates += (double)r->n * r->params.replicas * r->params.trials * (a.t_end - a.t_begin);
+        const int v = sweep_variant(a.alpha == 1, a.mode, a.nb);
+        const double np = a.prob.np;
+        const double cost = np * np * a.prob.planes * (a.t_end - a.t_begin + 1);
+        for (int c = 0; c < r->n_wg; ++c) lists[v].push_back({cost, ((uint32_t)i << 16) | (uint32_t)c});
+        max_np[v] = std::max(max_np[v], a.prob.np);
+        max_delay[v] = std::max(max_delay[v], a.delay);
+    }
+    s->work.clear();
+    size_t off[kVariants], len[kVariants];
+    for (int v = 0; v < kVariants; ++v) {
+        std::stable_sort(lists[v].begin(), lists[v].end(), [](const Entry& x, const Entry& y) { return x.cost > y.cost; });
+        off[v] = s->work.size();
+        len[v] = lists[v].size();
+        for (const Entry& e : lists[v]) s->work.push_back(e.code);
+    }
+    const size_t need = (sizeof(SweepArgs) * n + 255) / 256 * 256 + sizeof(uint32_t) * s->work.size();
+    if (need > s->table_bytes) {
+        if (s->table) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(s->table);
+        }
+        s->table = nullptr;
+        s->table_bytes = 0;
+        const size_t cap = need * 2;
+        if (hipMalloc(&s->table, cap) != hipSuccess) return fail(SSQA_ENOMEM, "launch table allocation failed");
+        s->table_bytes = cap;
+    }
+    auto* d_items = static_cast<SweepArgs*>(s->table);
+    auto* d_work = reinterpret_cast<uint32_t*>(static_cast<char*>(s->table) + (sizeof(SweepArgs) * n + 255) / 256 * 256);
+    SSQA_HIP(configure_sweep_kernels(), "configure");
+    SSQA_HIP(hipMemcpyAsync(d_items, s->items.data(), sizeof(SweepArgs) * n, hipMemcpyHostToDevice, stream), "upload");
+    SSQA_HIP(hipMemcpyAsync(d_work, s->work.data(), sizeof(uint32_t) * s->work.size(), hipMemcpyHostToDevice, stream),
+             "upload");
+    for (int v = 0; v < kVariants; ++v) {
+        if (!len[v]) continue;
+        SSQA_HIP(launch_sweep_batch(d_items, d_work + off[v], (int)len[v], max_np[v], max_delay[v], v, stream), "step");
+    }
+    // 3. read back and retire at the requests' own cycle boundaries
+    for (int i = 0; i < n; ++i) {
+        Request* r = s->active[i];
+        SSQA_HIP(hipMemcpyAsync(r->best.data(), s->items[i].best, sizeof(int64_t) * r->params.trials,
+                                hipMemcpyDeviceToHost, stream), "readback");
+        SSQA_HIP(hipMemcpyAsync(r->first_hit.data(), s->items[i].first_hit, sizeof(int32_t) * r->params.trials,
+                                hipMemcpyDeviceToHost, stream), "readback");
+    }
+    SSQA_HIP(hipStreamSynchronize(stream), "step");
+    s->cycles_run += K;
+    s->spin_updates += updates;
+    std::vector<Request*> still;
+    for (int i = 0; i < n; ++i) {
+        Request* r = s->active[i];
+        r->cycle = s->items[i].t_end;
+        bool done = r->cycle >= r->params.cycles;
+        if (!done && r->early_exit && r->params.target_energy != SSQA_NO_TARGET) {
+            for (int b = 0; b < r->params.trials && !done; ++b) done = r->best[b] == r->params.target_energy;
+        }
+        if (done) {
+            release_device(r);
+            s->bytes_in_use -= r->bytes;
+            r->state = SSQA_REQ_DONE;
+            r->done_s = now_s(s->t0);
+        } else {
+            still.push_back(r);
+        }
+    }
+    s->active.swap(still);
+    if (active_out) *active_out = (int32_t)s->active.size();
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_server_poll(ssqa_server_t s, int64_t id, ssqa_request_info* info, int64_t* best, int32_t* first_hit) {
+    g_last_error.clear();
+    if (!s || !info) return fail(SSQA_EINVAL, "NULL argument");
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return fail(SSQA_EINVAL, "unknown request %lld", (long long)id);
+    const Request* r = it->second.get();
+    info->state = r->state;
+    info->status = r->status;
+    info->cycles_done = r->cycle;
+    info->trials = r->params.trials;
+    info->submit_s = r->submit_s;
+    info->admit_s = r->admit_s;
+    info->done_s = r->done_s;
+    info->memory_bytes = r->bytes;
+    if (r->state == SSQA_REQ_DONE || r->state == SSQA_REQ_RUNNING) {
+        if (best && !r->best.empty()) std::memcpy(best, r->best.data(), sizeof(int64_t) * r->params.trials);
+        if (first_hit && !r->first_hit.empty())
+            std::memcpy(first_hit, r->first_hit.data(), sizeof(int32_t) * r->params.trials);
+    }
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_server_cancel(ssqa_server_t s, int64_t id) {
+    g_last_error.clear();
+    if (!s) return fail(SSQA_EINVAL, "server is NULL");
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return fail(SSQA_EINVAL, "unknown request %lld", (long long)id);
+    Request* r = it->second.get();
+    if (r->state == SSQA_REQ_QUEUED || r->state == SSQA_REQ_RUNNING) {
+        if (r->state == SSQA_REQ_QUEUED) r->done_s = now_s(s->t0);
+        r->state = SSQA_REQ_CANCELLED;
+    }
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_server_stats(ssqa_server_t s, ssqa_server_stats_t* out) {
+    g_last_error.clear();
+    if (!s || !out) return fail(SSQA_EINVAL, "NULL argument");
+    out->queued = (int32_t)s->queue.size();
+    out->active = (int32_t)s->active.size();
+    out->memory_in_use = s->bytes_in_use;
+    out->spin_updates = s->spin_updates;
+    out->elapsed_s = now_s(s->t0);
+    return SSQA_OK;
+}
+
+void ssqa_server_destroy(ssqa_server_t s) {
+    if (!s) return;
+    DeviceGuard guard(s->cfg.device);
+    for (auto& kv : s->all) release_device(kv.second.get());
+    if (s->table) (void)hipFree(s->table);
+    delete s;
+}
+
+}  // extern "C"
