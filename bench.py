@@ -52,7 +52,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512"])
+    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serve workload")
+    ap.add_argument("--serve-load", type=float, nargs="*", default=[0.5, 0.8],
+                    help="offered loads of the serve workload, as fractions of the measured saturation rate")
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batch512 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
@@ -168,6 +171,80 @@ def batched_vs_plain(args):
     }
 
 
+def serve_workload(args):
+    """Continuous batching under a Poisson arrival stream.  Request r solves a GI instance with
+    n drawn from {10, 20, 30, 40, 50, 100} (default_rng(7) over the request index; graph seed 5000 + r),
+    R = 32, T = 16, at most SC = 2000 cycles of the paper's schedule, early exit at E*, Philox seed r.
+    First all requests are submitted at once (saturation rate); then the stream is replayed at the
+    offered loads, reporting latency percentiles and sustained spin-updates/s."""
+    import numpy as np
+    import torch
+    import paper_2302_12454_amd as lib
+    from synth import WORKLOADS, poisson_arrivals, random_gi_pair
+
+    base = WORKLOADS["gi50"]
+    R, T, SC, K = 32, 16, 2000, 100
+    rng = np.random.default_rng(7)
+    sizes = rng.choice([10, 20, 30, 40, 50, 100], size=args.serve_requests)
+    q = lib.ssqa_jperp_schedule(SC, base.tau, base.beta, 0, 1, 2, base.scale)
+    i0 = np.full(SC, int(base.i0 * base.scale), dtype=np.int32)
+    noise = int(base.n_rnd * base.scale)
+    reqs = []
+    for r, n in enumerate(sizes):
+        pair = random_gi_pair(int(n), 0.5, 5000 + r)
+        h, J, e_star = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, base.scale)
+        reqs.append((h, J, dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=noise,
+                                delay=base.delay, seed=r, target=e_star)))
+    print(f"built {len(reqs)} requests", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+
+    def run(arrivals):
+        server = lib.Server(device=0, cycles_per_step=K, max_active=256, memory_budget=64 << 30)
+        ids = [None] * len(reqs)
+        t0 = time.perf_counter()
+        nxt = 0
+        steps = 0
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                h, J, kw = reqs[nxt]
+                ids[nxt] = server.submit(h, J, early_exit=True, **kw)
+                nxt += 1
+            st = server.stats()
+            if st["active"] or st["queued"]:
+                server.step(stream)
+                steps += 1
+            elif nxt < len(reqs):
+                time.sleep(max(0.0, min(0.01, arrivals[nxt] - now)))
+            else:
+                break
+        wall = time.perf_counter() - t0
+        infos = [server.poll(i) for i in ids]
+        lat = np.array([x["done_s"] - x["submit_s"] for x in infos])
+        solved = np.array([bool((x["best"] == kw["target"]).any()) for x, (_, _, kw) in zip(infos, reqs)])
+        updates = server.stats()["spin_updates"]
+        server.close()
+        return {"wall_s": wall, "steps": steps, "latency_p50_s": float(np.percentile(lat, 50)),
+                "latency_p99_s": float(np.percentile(lat, 99)), "latency_mean_s": float(lat.mean()),
+                "spin_updates_per_s": updates / wall, "solved_fraction": float(solved.mean()),
+                "completed": int(sum(x["state"] == "done" for x in infos))}
+
+    sat = run(np.zeros(len(reqs)))
+    rate = len(reqs) / sat["wall_s"]
+    print(f"saturation {rate:.2f} req/s", file=sys.stderr, flush=True)
+    loads = []
+    for frac in args.serve_load:
+        arrivals = poisson_arrivals(len(reqs), rate * frac, seed=11)
+        res = run(arrivals)
+        res.update({"offered_load": frac, "qps": rate * frac})
+        loads.append(res)
+        print(f"load {frac}: p50 {res['latency_p50_s']:.3f} s p99 {res['latency_p99_s']:.3f} s",
+              file=sys.stderr, flush=True)
+    return {"workload": f"serve: {len(reqs)} GI requests, n in {{10,20,30,40,50,100}}, R={R}, T={T}, "
+                        f"SC<={SC}, K={K} cycles per step, early exit at E*",
+            "saturation": dict(sat, qps=rate), "loads": loads}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -185,6 +262,9 @@ def main():
 
     if args.workload == "batch512":
         print(json.dumps({"metric": METRIC, "batched_vs_plain": batched_vs_plain(args)}), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps({"metric": METRIC, "served": serve_workload(args)}), flush=True)
         return
     wl = WORKLOADS[args.workload]
     pair = random_gi_pair(wl.n, wl.p, wl.graph_seed)
