@@ -4,7 +4,10 @@ One step is one complete anneal of the workload (every cycle of Eq. 6a-c for all
 trials, plus the final energy pass), through the C ABI, with the problem already
 resident on the GPU.  Default workload: GI with n = 50 (N = 2500 spins), G(50, 0.5)
 plus a relabelled copy (graph seed 2), R = 64 replicas, T = 1024 trials, SC = 2000
-cycles, the paper's SSQA schedule (Table 2, tau = 100) at integer scale 12.
+cycles, the paper's SSQA schedule (Table 2, tau = 100) at integer scale 12.  The
+default line also carries the oracle's CPU baseline and the batched-vs-plain
+comparison on 512 uneven GI instances (--workload batch512 alone); --workload serve
+runs the continuous-batching server under Poisson arrivals.
 
 Prints one JSON line (rank 0).  --gpus N with N > 1 is refused: this build runs on
 one GPU; see the design notes for how trials would be sharded across GPUs.
@@ -52,12 +55,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512", "serve"])
+    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512", "serve", "sweeps"])
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serve workload")
     ap.add_argument("--serve-load", type=float, nargs="*", default=[0.5, 0.8],
                     help="offered loads of the serve workload, as fractions of the measured saturation rate")
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batch512 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain comparison on 512 uneven GI instances")
     ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (scale for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -245,6 +250,88 @@ def serve_workload(args):
             "saturation": dict(sat, qps=rate), "loads": loads}
 
 
+def sweeps_workload(args):
+    """The paper's experimental design on synthetic GI instances (n = 30, 40, 50; graph seeds 30, 40, 50),
+    100 trials each, the SSQA schedule of Table 2:
+      * Table 3 / Fig. 8: R = 25 with (EC, tau) = (10k, 50), (10k, 100), (20k, 50), (20k, 100), (40k, 100);
+      * Figs. 6-7: R in {5, 10, 20, 25, 30, 40, 50} at EC = 20k and 40k (tau = 100), SC = EC / R;
+      * Fig. 5: energy of replicas 1, 10 and 20 over four iterations (N = 2500, R = 25, tau = 100).
+    All anneals of the two sweeps run as one batch; each is also run alone (plain) to give its own t for
+    the TTS of Eq. 10."""
+    import numpy as np
+    import torch
+    import paper_2302_12454_amd as lib
+    from synth import WORKLOADS, random_gi_pair
+
+    base = WORKLOADS["gi50"]
+    T = 100
+    noise = int(base.n_rnd * base.scale)
+    configs = []
+    for n in (30, 40, 50):
+        for ec, tau in ((10000, 50), (10000, 100), (20000, 50), (20000, 100), (40000, 100)):
+            configs.append(("table3", n, 25, ec, tau))
+        for ec in (20000, 40000):
+            for R in (5, 10, 20, 25, 30, 40, 50):
+                configs.append(("r_sweep", n, R, ec, 100))
+    problems = {}
+    for n in (30, 40, 50):
+        pair = random_gi_pair(n, 0.5, n)
+        h, J, e_star = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, base.scale)
+        problems[n] = (lib.Problem(h, J, device=0), e_star)
+    jobs = []
+    for kind, n, R, ec, tau in configs:
+        SC = ec // R
+        q = lib.ssqa_jperp_schedule(SC, tau, base.beta, 0, 1, 2, base.scale)
+        i0 = np.full(SC, int(base.i0 * base.scale), dtype=np.int32)
+        prob, e_star = problems[n]
+        jobs.append((prob, dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=noise,
+                                delay=base.delay, seed=len(jobs), target=e_star)))
+    stream = torch.cuda.current_stream()
+    batch = lib.Batch(jobs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    res = batch.run(stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    batched_ms = ev[0].elapsed_time(ev[1])
+    rows = []
+    plain_total = 0.0
+    for (kind, n, R, ec, tau), (prob, kw), r in zip(configs, jobs, res):
+        e_star = kw["target"]
+        p_s = float((r.best_energy.cpu().numpy() == e_star).mean())
+        ev[0].record(stream)
+        lib.ssqa_anneal(prob, stream=stream, **kw)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / 1e3
+        plain_total += t
+        tts = None if p_s <= 0 else (0.0 if p_s >= 1 else t * math.log(0.01) / math.log(1 - p_s))
+        rows.append({"kind": kind, "N": n * n, "R": R, "EC": ec, "tau": tau, "SC": ec // R,
+                     "iterations": ec / R / (tau * (base.beta + 1)), "p_s": p_s, "t_plain_s": t, "tts99_s": tts})
+    batch.close()
+    # Fig. 5: one anneal with the energy trace
+    prob, e_star = problems[50]
+    SC = 1600
+    q = lib.ssqa_jperp_schedule(SC, 100, base.beta, 0, 1, 2, base.scale)
+    i0 = np.full(SC, int(base.i0 * base.scale), dtype=np.int32)
+    tr = lib.ssqa_anneal(prob, replicas=25, trials=1, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=noise,
+                         delay=base.delay, seed=5, target=e_star, trace=True)
+    torch.cuda.synchronize()
+    energy = tr.energy_trace.cpu().numpy()[:, 0, :]        # [SC + 1, R]
+    waveform = {}
+    for k in (0, 9, 19):
+        e = energy[:, k]
+        hits = np.nonzero(e == e_star)[0]
+        waveform[f"replica_{k + 1}"] = {
+            "min_energy_per_iteration": [int(e[it * 400:(it + 1) * 400 + 1].min()) for it in range(4)],
+            "first_cycle_at_ground": int(hits[0]) if len(hits) else None,
+            "cycles_at_ground": int(len(hits))}
+    return {"workload": "sweeps: GI n = 30, 40, 50 (graph seeds 30, 40, 50), T = 100 trials",
+            "anneals": len(jobs), "batched_ms": batched_ms, "plain_total_ms": plain_total * 1e3,
+            "e_star": {str(n * n): int(problems[n][1]) for n in problems}, "rows": rows,
+            "fig5_waveform_N2500_R25": waveform}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -265,6 +352,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps({"metric": METRIC, "served": serve_workload(args)}), flush=True)
+        return
+    if args.workload == "sweeps":
+        print(json.dumps({"metric": METRIC, "sweeps": sweeps_workload(args)}), flush=True)
         return
     wl = WORKLOADS[args.workload]
     pair = random_gi_pair(wl.n, wl.p, wl.graph_seed)
@@ -353,6 +443,10 @@ def main():
     if not args.no_cpu_baseline:
         num_j = np.asarray(J)
         result["cpu_baseline"] = cpu_baseline(h, num_j, e_star, wl, q, i0, args.cpu_sample_cycles)
+    if not args.no_batched and args.workload == "gi50":
+        del out, prob
+        torch.cuda.empty_cache()
+        result["batched_vs_plain"] = batched_vs_plain(args)
     print(json.dumps(result), flush=True)
 
 
