@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 INT8_MFMA_PEAK = 5.0e15      # MI355X dense int8 MFMA, ops/s
+FP4_MFMA_PEAK = 10.1e15      # MI355X dense fp4 MFMA, flop/s
 HBM_PEAK = 8.0e12            # bytes/s
 
 METRIC = "spin-updates/s and time-to-solution @99% success (N=2500 GI), batched vs plain"
@@ -34,9 +35,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_12454_amd", "csrc", "sweep.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_gi50_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the sweep kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-    or None when the kernel source changed since those counters were taken."""
+def measured_traffic(dtype):
+    """HBM bytes per launch of the sweep kernel (with `dtype` operands) from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source changed since those counters were taken
+    or none were taken for these operands."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -45,7 +47,7 @@ def measured_traffic():
             digest = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != digest:
+    if rec.get("kernel_source_sha256") != digest or rec.get("operands", "int8") != dtype:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -61,6 +63,8 @@ def parse():
                     help="offered loads of the serve workload, as fractions of the measured saturation rate")
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batch512 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--operands", default="auto", choices=["auto", "int8", "fp4"],
+                    help="field-product operands of the main line (auto: fp4 when J is exactly representable)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison on 512 uneven GI instances")
     ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
@@ -365,6 +369,10 @@ def main():
     noise = int(wl.n_rnd * wl.scale)
     prob = lib.Problem(h, J, device=0)
     N, R, T, SC = wl.spins, wl.replicas, wl.trials, wl.cycles
+    fmt = {"auto": 0, "int8": 1, "fp4": 2}[args.operands]
+    if fmt == 0:
+        fmt = 2 if prob.fp4_exact else 1
+    dtype, peak = ("fp4", FP4_MFMA_PEAK) if fmt == 2 else ("int8", INT8_MFMA_PEAK)
 
     dev = torch.device("cuda", 0)
     out = lib.AnnealResult(best_energy=torch.empty(T, dtype=torch.int64, device=dev),
@@ -375,7 +383,7 @@ def main():
     def step():
         lib.ssqa_anneal(prob, replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=wl.alpha, noise_amp=noise,
                         delay=wl.delay, seed=wl.seed, coupling_mode=wl.coupling_mode, target=e_star,
-                        stream=stream, out=out)
+                        operand_format=fmt, stream=stream, out=out)
 
     for w in range(args.warmup):
         step()
@@ -423,7 +431,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: GI n={wl.n} (N={N} spins), G({wl.n},{wl.p}) + relabelled copy "
                                f"(graph seed {wl.graph_seed}), R={R}, T={T}, SC={SC}, tau={wl.tau}, "
@@ -433,8 +441,8 @@ def main():
         "e_star": int(e_star),
         "tts99_s_per_trial_amortised": tts(sec / T),
         "tts99_s_latency_form": tts(sec),
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / INT8_MFMA_PEAK, "traffic": measured_traffic(),
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dtype),
                      "kernel": "sweep_kernel", "ops_per_launch": ops},
         "paper_context": {"ssqa_N2500": {"p_s": 0.41, "t_s": 46.4, "tts99_s": 405,
                                          "hardware": "MATLAB R2020b, AMD Ryzen 9 5950X", "R": 25, "SC": 1600,

@@ -66,7 +66,9 @@ typedef struct ssqa_problem* ssqa_problem_t;
  *             diagonal (only i != j pairs couple, Eq. 1 sums over i < j).
  *   out     : receives the handle.
  * J is stored as P signed int8 planes with J = sum_p 256^p J_p (P = 1 when every |J_ij| <= 127),
- * zero-padded to a multiple of 128 rows and columns.
+ * zero-padded to a multiple of 128 rows and columns, and additionally as fp4 (e2m1) when every J_ij is
+ * one of 0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J_ij| is below 2^24 (then the fp4 field
+ * product with fp32 accumulation is exact).
  * Fails with SSQA_EINVAL for a bad size, pointer or non-symmetric J, and with SSQA_ERANGE when
  * 2 * sum_i |h_i| + sum_ij |J_ij| >= 2^30 (energies and fields must stay inside int32).
  */
@@ -76,10 +78,13 @@ ssqa_status ssqa_create_problem(int32_t n_spins, const int32_t* h, const int32_t
 /* Release the problem's device memory.  NULL is ignored.  No call may still be using it. */
 void ssqa_destroy_problem(ssqa_problem_t problem);
 
-/* N, the number of int8 planes P, and the padded size of the device layout. */
+/* N, the number of int8 planes P, the padded size of the device layout, and 1 when the fp4 copy of
+ * J exists (operand_format 2 is then available and is what operand_format 0 picks), else 0.  A NULL
+ * handle gives 0. */
 int32_t ssqa_problem_spins(ssqa_problem_t problem);
 int32_t ssqa_problem_planes(ssqa_problem_t problem);
 int32_t ssqa_problem_padded(ssqa_problem_t problem);
+int32_t ssqa_problem_fp4_exact(ssqa_problem_t problem);
 
 /* ------------------------------------------------------------------------------------------- */
 /* Annealing.                                                                                  */
@@ -105,6 +110,11 @@ typedef struct ssqa_anneal_params {
     int32_t block_columns;     /* columns (whole trials) per workgroup: 0 = automatic (64 when R <= 64
                                   and the bit planes fit in LDS, else 32), or 32 / 64.  A tiling
                                   choice only: results do not depend on it                        */
+    int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when every J_ij is one of
+                                  0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J| is below 2^24,
+                                  else int8 planes); 1 = int8 planes; 2 = fp4 (e2m1, fp32
+                                  accumulation, exact under the same conditions; SSQA_ENOTSUP
+                                  otherwise).  Results do not depend on it                         */
 } ssqa_anneal_params;
 
 typedef struct ssqa_anneal_outputs {
@@ -251,6 +261,18 @@ void ssqa_server_destroy(ssqa_server_t server);
  */
 ssqa_status ssqa_energy(ssqa_problem_t problem, const int8_t* spins, int32_t cols, int64_t* energies,
                         void* hip_stream);
+
+/*
+ * QMC Hamiltonian (Eq. 4) of `trials` trials of `replicas` replicas from their counters, exactly:
+ *   H_c = sum_k H_p(sigma_k) - J_perp sum_k sum_i sigma_{i,k} sigma_{i,(k+1) mod R},
+ * with sigma = +1 where the counter is >= 0 (Eq. 6c).
+ *   counters : device int8 [trials * replicas * N] in the layout of ssqa_anneal's final_is.
+ *   jperp    : J_perp at the integer scale.
+ *   energies : device int64 [trials].
+ * Asynchronous on `stream`.
+ */
+ssqa_status ssqa_qmc_energy(ssqa_problem_t problem, const int8_t* counters, int32_t trials, int32_t replicas,
+                            int32_t jperp, int64_t* energies, void* hip_stream);
 
 /* ------------------------------------------------------------------------------------------- */
 /* Host helpers: schedules and the graph-isomorphism mapping (no device work).                 */

@@ -20,6 +20,7 @@ from .api import (  # noqa: F401
     ssqa_gi_to_ising,
     ssqa_jperp_schedule,
     ssqa_philox4x32_10,
+    ssqa_qmc_energy,
     ssqa_server_create,
     ssqa_ssa_i0_schedule,
 )

@@ -29,6 +29,7 @@ class AnnealParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("target_energy", ctypes.c_int64),
         ("block_columns", ctypes.c_int32),
+        ("operand_format", ctypes.c_int32),
     ]
 
 
@@ -93,10 +94,13 @@ SIGNATURES = {
     "ssqa_problem_spins": (ctypes.c_int32, [ctypes.c_void_p]),
     "ssqa_problem_planes": (ctypes.c_int32, [ctypes.c_void_p]),
     "ssqa_problem_padded": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ssqa_problem_fp4_exact": (ctypes.c_int32, [ctypes.c_void_p]),
     "ssqa_anneal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams),
                                    ctypes.POINTER(AnnealOutputs), ctypes.c_void_p]),
     "ssqa_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p]),
+    "ssqa_qmc_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "ssqa_jperp_schedule": (ctypes.c_int, [ctypes.c_int32] * 7 + [c_int32_p]),
     "ssqa_ssa_i0_schedule": (ctypes.c_int, [ctypes.c_int32] * 6 + [c_int32_p]),
     "ssqa_gi_to_ising": (ctypes.c_int, [ctypes.c_int32, c_uint8_p, c_uint8_p, ctypes.c_int32, ctypes.c_int32,

@@ -69,6 +69,10 @@ class Problem:
     def padded(self) -> int:
         return int(_lib.load().ssqa_problem_padded(self._handle))
 
+    @property
+    def fp4_exact(self) -> bool:
+        return bool(_lib.load().ssqa_problem_fp4_exact(self._handle))
+
     def close(self) -> None:
         if getattr(self, "_handle", None) is not None and self._handle.value:
             _lib.load().ssqa_destroy_problem(self._handle)
@@ -112,7 +116,7 @@ def _alloc_outputs(problem: Problem, trials: int, replicas: int, cycles: int, tr
 
 
 def _params(*, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, seed, coupling_mode=0, target=None,
-            cycles_per_launch=0, block_columns=0):
+            cycles_per_launch=0, block_columns=0, operand_format=0):
     jperp = _i32(jperp)
     i0 = _i32(i0)
     if len(jperp) < cycles or len(i0) < cycles:
@@ -126,6 +130,7 @@ def _params(*, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, see
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.target_energy = SSQA_NO_TARGET if target is None else int(target)
     p.block_columns = int(block_columns)
+    p.operand_format = int(operand_format)
     return p, (jperp, i0)          # keep the arrays alive as long as the struct
 
 
@@ -141,7 +146,7 @@ def _outputs(out: AnnealResult):
 def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
                 noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
                 trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, block_columns: int = 0,
-                stream=None, out: AnnealResult | None = None) -> AnnealResult:
+                operand_format: int = 0, stream=None, out: AnnealResult | None = None) -> AnnealResult:
     """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
     current stream).  ``out`` may carry preallocated outputs of the right shapes."""
     lib = _lib.load()
@@ -149,7 +154,8 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
         out = _alloc_outputs(problem, trials, replicas, cycles, trace, final_is)
     p, keep = _params(replicas=replicas, trials=trials, cycles=cycles, jperp=jperp, i0=i0, alpha=alpha,
                       noise_amp=noise_amp, delay=delay, seed=seed, coupling_mode=coupling_mode, target=target,
-                      cycles_per_launch=cycles_per_launch, block_columns=block_columns)
+                      cycles_per_launch=cycles_per_launch, block_columns=block_columns,
+                      operand_format=operand_format)
     o = _outputs(out)
     _check(lib.ssqa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
            "ssqa_anneal")
@@ -223,6 +229,20 @@ def ssqa_energy(problem: Problem, spins, stream=None):
     energies = torch.empty(cols, dtype=torch.int64, device=spins.device)
     _check(lib.ssqa_energy(problem.handle, ctypes.c_void_p(spins.data_ptr()), cols,
                            ctypes.c_void_p(energies.data_ptr()), _stream_handle(stream)), "ssqa_energy")
+    return energies
+
+
+def ssqa_qmc_energy(problem: Problem, counters, jperp: int, stream=None):
+    """QMC Hamiltonian (Eq. 4) per trial from counters (torch int8 [T, R, N] on the device) -> int64 [T]."""
+    import torch
+    lib = _lib.load()
+    counters = counters.contiguous()
+    if counters.dtype != torch.int8 or counters.dim() != 3 or counters.shape[2] != problem.n:
+        raise ValueError("counters must be int8 [T, R, N]")
+    T, R = int(counters.shape[0]), int(counters.shape[1])
+    energies = torch.empty(T, dtype=torch.int64, device=counters.device)
+    _check(lib.ssqa_qmc_energy(problem.handle, ctypes.c_void_p(counters.data_ptr()), T, R, int(jperp),
+                               ctypes.c_void_p(energies.data_ptr()), _stream_handle(stream)), "ssqa_qmc_energy")
     return energies
 
 

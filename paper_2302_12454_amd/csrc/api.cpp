@@ -67,6 +67,11 @@ int planes_needed(int32_t v) {
     return p;
 }
 
+bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    if (pa->operand_format == 1) return false;
+    return prob->dev.J4 != nullptr;
+}
+
 // Columns per workgroup: the requested width, or 64 when R <= 64 and the bit planes fit in LDS, else 32.
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
     if (pa->block_columns == 32 || pa->block_columns == 64) return pa->block_columns;
@@ -79,6 +84,9 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
     if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
     if (pa->block_columns != 0 && pa->block_columns != 32 && pa->block_columns != 64)
         return fail(SSQA_EINVAL, "block_columns must be 0, 32 or 64");
+    if (pa->operand_format < 0 || pa->operand_format > 2) return fail(SSQA_EINVAL, "operand_format must be 0, 1 or 2");
+    if (pa->operand_format == 2 && !prob->dev.J4)
+        return fail(SSQA_ENOTSUP, "fp4 operands requested but J has entries outside {0, +-1, +-2, +-3, +-4, +-6}");
     const int nb = block_columns(prob, pa);
     if (R > nb) return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d columns per workgroup", R, nb);
     if ((long long)T * R > (1LL << 28)) return fail(SSQA_EINVAL, "trials * replicas too large");
@@ -108,6 +116,7 @@ SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, cons
     const int tpw = nb / pa->replicas;
     a.prob = prob->dev;
     a.nb = nb;
+    a.fp4 = use_fp4(prob, pa) ? 1 : 0;
     a.R = pa->replicas;
     a.T = pa->trials;
     a.tpw = tpw;
@@ -168,16 +177,22 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     if (!h || !J) return fail(SSQA_EINVAL, "h or J is NULL");
     long long total = 0;
     int planes = 1;
+    bool fp4_exact = true;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6} and every row sum of |J| < 2^24
     for (int i = 0; i < n; ++i) {
         total += 2LL * std::llabs((long long)h[i]);
+        long long row_abs = 0;
         if (J[(size_t)i * n + i] != 0) return fail(SSQA_EINVAL, "J[%d][%d] = %d, diagonal must be zero", i, i,
                                                    J[(size_t)i * n + i]);
         for (int j = 0; j < n; ++j) {
             const int32_t v = J[(size_t)i * n + j];
             if (v != J[(size_t)j * n + i]) return fail(SSQA_EINVAL, "J not symmetric at (%d, %d)", i, j);
             total += std::llabs((long long)v);
+            row_abs += std::llabs((long long)v);
             planes = std::max(planes, planes_needed(v));
+            const int m = v < 0 ? -v : v;
+            if (m > 6 || m == 5) fp4_exact = false;
         }
+        if (row_abs >= (1LL << 24)) fp4_exact = false;
         if (total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
     }
     int dev_count = 0;
@@ -194,13 +209,16 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     int32_t* J32 = nullptr;
     int32_t* h32 = nullptr;
     const size_t plane_bytes = (size_t)planes * np * np;
+    const int kp4 = (np + 255) / 256 * 256;
     hipError_t e = hipMalloc(&p->J_planes, plane_bytes);
+    if (e == hipSuccess && fp4_exact) e = hipMalloc(&p->J_fp4, (size_t)np * kp4 / 2);
     if (e == hipSuccess) e = hipMalloc(&p->rowvec, (size_t)np * 4 * 3);
     if (e == hipSuccess) e = hipMalloc(&J32, (size_t)n * n * 4);
     if (e == hipSuccess) e = hipMalloc(&h32, (size_t)n * 4);
     if (e == hipSuccess) e = hipMemcpy(J32, J, (size_t)n * n * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h32, h, (size_t)n * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_prepare_planes(J32, h32, n, np, planes, p->J_planes, p->rowvec, nullptr);
+    if (e == hipSuccess && fp4_exact) e = launch_prepare_fp4(J32, n, np, kp4, p->J_fp4, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (J32) (void)hipFree(J32);
     if (h32) (void)hipFree(h32);
@@ -213,6 +231,8 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     p->dev.np = np;
     p->dev.planes = planes;
     p->dev.J = p->J_planes;
+    p->dev.J4 = p->J_fp4;
+    p->dev.kp4 = kp4;
     p->dev.h = p->rowvec;
     p->dev.hr = p->rowvec + np;
     p->dev.er = p->rowvec + 2 * np;
@@ -224,6 +244,7 @@ void ssqa_destroy_problem(ssqa_problem_t p) {
     if (!p) return;
     DeviceGuard guard(p->device);
     if (p->J_planes) (void)hipFree(p->J_planes);
+    if (p->J_fp4) (void)hipFree(p->J_fp4);
     if (p->rowvec) (void)hipFree(p->rowvec);
     delete p;
 }
@@ -231,6 +252,7 @@ void ssqa_destroy_problem(ssqa_problem_t p) {
 int32_t ssqa_problem_spins(ssqa_problem_t p) { return p ? p->dev.n : 0; }
 int32_t ssqa_problem_planes(ssqa_problem_t p) { return p ? p->dev.planes : 0; }
 int32_t ssqa_problem_padded(ssqa_problem_t p) { return p ? p->dev.np : 0; }
+int32_t ssqa_problem_fp4_exact(ssqa_problem_t p) { return p && p->J_fp4 ? 1 : 0; }
 
 ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
                         void* hip_stream) {
@@ -349,7 +371,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         double cost;
         uint32_t code;
     };
-    constexpr int kVariants = 8;
+    constexpr int kVariants = kSweepVariants;
     std::vector<Entry> lists[kVariants];
     int max_np[kVariants] = {}, max_delay[kVariants] = {};
     for (int i = 0; i < count; ++i) {
@@ -367,7 +389,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         items[i].t_end = SC;
         items[i].final_pass = 1;
         io += (size_t)n_wg[i] * nbs[i] * problems[i]->dev.np;
-        const int v = sweep_variant(pa.alpha == 1, pa.coupling_mode, nbs[i]);
+        const int v = sweep_variant(pa.alpha == 1, pa.coupling_mode, nbs[i], items[i].fp4 != 0);
         const double np = problems[i]->dev.np;
         const double cost = np * np * problems[i]->dev.planes * (SC + 1.0);
         for (int c = 0; c < n_wg[i]; ++c) lists[v].push_back({cost, ((uint32_t)i << 16) | (uint32_t)c});
@@ -450,6 +472,20 @@ ssqa_status ssqa_energy(ssqa_problem_t prob, const int8_t* spins, int32_t cols, 
     DeviceGuard guard(prob->device);
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
     SSQA_HIP(launch_energy(prob->dev, spins, cols, energies, reinterpret_cast<hipStream_t>(hip_stream)), "energy");
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_qmc_energy(ssqa_problem_t prob, const int8_t* counters, int32_t trials, int32_t replicas,
+                            int32_t jperp, int64_t* energies, void* hip_stream) {
+    g_last_error.clear();
+    if (!prob || !counters || !energies) return fail(SSQA_EINVAL, "NULL argument");
+    if (trials < 0 || replicas < 1) return fail(SSQA_EINVAL, "trials must be >= 0 and replicas >= 1");
+    if (jperp < -(1 << 20) || jperp > (1 << 20)) return fail(SSQA_EINVAL, "jperp outside [-2^20, 2^20]");
+    if (trials == 0) return SSQA_OK;
+    DeviceGuard guard(prob->device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
+    SSQA_HIP(launch_qmc_energy(prob->dev, counters, trials, replicas, jperp, energies,
+                               reinterpret_cast<hipStream_t>(hip_stream)), "qmc_energy");
     return SSQA_OK;
 }
 

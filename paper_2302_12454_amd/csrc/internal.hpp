@@ -27,12 +27,31 @@ __host__ __device__ inline size_t tiled_offset(int i, int j, int np) {
     return ((size_t)(r * nsteps + s) * 8 + ai) * 1024 + (size_t)lane * 16 + byte;
 }
 
+// Byte offset and nibble of J_ij in the fp4 copy (K steps of 128 for v_mfma_scale_f32_16x16x128_f8f6f4).
+// Block (row tile r, K step s, fragment ai) is 1 KiB; lane = 16 g + slot holds 32 values of row slot
+// (tile row 32 (slot / 4) + 4 ai + slot % 4) for K = 128 s + 32 g + o, o < 32.  Value o = 16 h + 4 d + m
+// sits in byte 4 d + m, nibble h, so that operand dword d holds the K offsets whose bit-plane positions
+// are congruent to d modulo 4 (see the sweep kernel).
+__host__ __device__ inline size_t tiled_offset_fp4(int i, int j, int kp4, int* nibble) {
+    const int nsteps = kp4 / 128;
+    const int r = i >> 7, orow = i & 127;
+    const int slot = 4 * (orow >> 5) + (orow & 3);
+    const int ai = (orow & 31) >> 2;
+    const int s = j >> 7, g = (j & 127) >> 5, o = j & 31;
+    const int h = o >> 4, d = (o >> 2) & 3, m = o & 3;
+    *nibble = h;
+    return ((size_t)(r * nsteps + s) * 8 + ai) * 1024 + (size_t)(g * 16 + slot) * 16 + 4 * d + m;
+}
+
 // Device-side description of one problem.
 struct DeviceProblem {
     int32_t n;          // spins N
     int32_t np;         // N padded to a multiple of kTileRows (rows and columns of every plane)
     int32_t planes;     // P int8 planes, J = sum_p 256^p J_p
     const int8_t* J;    // [P][np * np] in the fragment-tiled layout of tiled_offset, zero padded
+    const uint8_t* J4;  // fp4 (e2m1) copy of J in the layout of tiled_offset_fp4 when every J_ij is exactly
+                        // representable (0, +-1, +-2, +-3, +-4, +-6), else nullptr
+    int32_t kp4;        // K extent of the fp4 copy: np rounded up to a multiple of 256
     const int32_t* h;   // [np], zero padded
     const int32_t* hr;  // [np]: h_i - sum_j J_ij   (field offset for x = (sigma + 1) / 2)
     const int32_t* er;  // [np]: 2 h_i - sum_j J_ij (energy offset)
@@ -42,6 +61,7 @@ struct DeviceProblem {
 struct SweepArgs {
     DeviceProblem prob;
     int32_t nb;             // columns per workgroup: 64 or 32
+    int32_t fp4;            // 1: the field product runs on the fp4 copy of J
     int32_t R;              // replicas
     int32_t T;              // trials
     int32_t tpw;            // trials per workgroup
@@ -68,12 +88,15 @@ struct SweepArgs {
 // rowvec receives [h | hr | er], three int32 vectors of np entries.
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
                                  int8_t* Jp, int32_t* rowvec, hipStream_t stream);
+// fp4 copy of J (every entry must be one of 0, +-1, +-2, +-3, +-4, +-6): np rows by kp4 columns.
+hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4, hipStream_t stream);
 // Sets the LDS limits of every sweep kernel variant once (before any launch or graph capture).
 hipError_t configure_sweep_kernels();
 // Dynamic LDS of one sweep workgroup for padded size np, delay d and nb columns.
 size_t sweep_lds_bytes(int np, int delay, int nb);
-// Kernel variant index of (alpha == 1, coupling mode, nb).
-int sweep_variant(bool alpha1, int mode, int nb);
+// Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.
+constexpr int kSweepVariants = 16;
+int sweep_variant(bool alpha1, int mode, int nb, bool fp4);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
 // items: device array of anneals; work: device list of (item << 16 | column block), n_work entries, all of
 // one kernel variant; the LDS size is taken for the largest padded N and delay among them.
@@ -83,6 +106,8 @@ hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, i
                                 int32_t tpw, int32_t nb, int8_t* out, hipStream_t stream);
 hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t cols, int64_t* energies,
                          hipStream_t stream);
+hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, int32_t trials, int32_t R,
+                             int32_t jperp, int64_t* out, hipStream_t stream);
 
 }  // namespace ssqa
 
@@ -97,6 +122,7 @@ struct ssqa_problem {
     int32_t device;
     ssqa::DeviceProblem dev;
     int8_t* J_planes;
+    uint8_t* J_fp4;    // fp4 copy of J, or nullptr
     int32_t* rowvec;   // [h | h - rowsum | 2h - rowsum], np each
 };
 
@@ -116,6 +142,8 @@ struct DeviceGuard {
     ~DeviceGuard();
 };
 
+// Whether an anneal of `prob` with `pa` runs its field product on the fp4 copy of J.
+bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Columns per workgroup for an anneal of `prob` with `pa` (64 or 32).
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Full argument check of one anneal; records the reason on failure.

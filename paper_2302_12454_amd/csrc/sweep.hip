@@ -50,6 +50,22 @@ __device__ inline uint32_t spread_bits(uint32_t natural) {
     return r;
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+// fp4 (e2m1) operand of x = (sigma + 1) / 2 from one bit-plane word: 1.0 is nibble 0b0010.  Dword d takes
+// the bits at positions congruent to d modulo 4, one per nibble (see tiled_offset_fp4 for the matching J).
+__device__ __forceinline__ v4i expand_operand_fp4(uint32_t w) {
+    v4i r;
+    r[0] = (int)((w << 1) & 0x22222222u);
+    r[1] = (int)(w & 0x22222222u);
+    r[2] = (int)((w >> 1) & 0x22222222u);
+    r[3] = (int)((w >> 2) & 0x22222222u);
+    return r;
+}
+
+__device__ __forceinline__ v8i widen(const v4i& x) { return __builtin_shufflevector(x, x, 0, 1, 2, 3, -1, -1, -1, -1); }
+
 __device__ __forceinline__ v4i expand_operand(uint32_t w) {
     // w already shifted by 4 h; bytes are x = (sigma + 1) / 2 in {0, 1}
     v4i r;
@@ -185,7 +201,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const 
 //   best    [kNB]   int64               per-trial best energy
 //   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
 // All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
-template <bool kAlpha1, int kMode, int kNBF>
+template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     constexpr int kNB = 16 * kNBF;
     extern __shared__ uint32_t lds[];
@@ -290,6 +306,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     // Buffer resource over all J planes (gfx9 raw buffer, byte addressed).
     const __amdgpu_buffer_rsrc_t jrsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(a.prob.J), 0, P * np * np, 0x00020000);
+    const __amdgpu_buffer_rsrc_t j4rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(a.prob.J4), 0, kFp4 ? np * (a.prob.kp4 / 2) : 0, 0x00020000);
 
     for (int t = a.t_begin; t <= a.t_end; ++t) {
         const bool update = t < a.t_end;
@@ -314,68 +332,133 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                 for (int f = 0; f < kNBF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
 
-            // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
-            // group g ends up with rows 32 g .. 32 g + 31.
-            const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
-            const int bsh = 4 * (g & 1);
-            for (int p = P - 1; p >= 0; --p) {
-                if (p < P - 1) {
+            if constexpr (kFp4) {
+                // Field product on the fp4 copy of J: K steps of 128, fp32 accumulators (exact: every partial
+                // sum is an integer far below 2^24), converted to int for the epilogue.
+                v4f accf[8][kNBF];
 #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai)
+                for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) acc[ai][f] = acc[ai][f] * 256;
-                }
-                // J is read through a buffer resource (loads past the planes return 0 instead of faulting), one
-                // contiguous 1 KiB fragment per load.  One A buffer: the loads of step s + 1 are issued right
-                // behind the MFMAs of step s that read the same registers, so their latency overlaps the rest of
-                // the MFMA pipeline.
+                    for (int f = 0; f < kNBF; ++f) accf[ai][f] = v4f{0.f, 0.f, 0.f, 0.f};
+                const int nsteps4 = a.prob.kp4 / 128;          // even
+                const uint32_t* bsrc = pl_cur + col16 * cstride;
+                const int wlast = words - 1;
                 const int voff = lane * 16;
-                const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
-                // Two A buffers, loads issued two K steps ahead: buffer b holds step s while the loads of step
-                // s + 2 refill it right behind the MFMAs that read it.
+                const int tile_off = tile * nsteps4 * 8 * 1024;
                 v4i A0[8], A1[8];
 #pragma unroll
-                for (int ai = 0; ai < 8; ++ai) A0[ai] = load_j(jrsrc, voff, tile_off + ai * 1024);
+                for (int ai = 0; ai < 8; ++ai) A0[ai] = load_j(j4rsrc, voff, tile_off + ai * 1024);
 #pragma unroll
-                for (int ai = 0; ai < 8; ++ai) A1[ai] = load_j(jrsrc, voff, tile_off + (8 + ai) * 1024);
+                for (int ai = 0; ai < 8; ++ai) A1[ai] = load_j(j4rsrc, voff, tile_off + (8 + ai) * 1024);
                 uint32_t bw[kNBF];
 #pragma unroll
-                for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
-                // Drain the first loads here: at the loop head the loads in flight are then exactly the ones the
-                // previous steps issued in fragment order, so each MFMA group waits for its own fragment only.
-                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-                for (int s = 0; s < nsteps; s += 2) {
-                    // step s from A0 (nsteps is even)
+                for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(g, wlast)];
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
+                for (int s = 0; s < nsteps4; s += 2) {
                     {
                         v4i B[kNBF];
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
+                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * (s + 1)];
-                        const int s_ld = s + 2 < nsteps ? s + 2 : nsteps - 1;
+                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(4 * (s + 1) + g, wlast)];
+                        const int s_ld = s + 2 < nsteps4 ? s + 2 : nsteps4 - 1;
 #pragma unroll
                         for (int ai = 0; ai < 8; ++ai) {
 #pragma unroll
                             for (int f = 0; f < kNBF; ++f)
-                                acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0[ai], B[f], acc[ai][f], 0, 0, 0);
-                            A0[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                                accf[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                                    widen(A0[ai]), widen(B[f]), accf[ai][f], 4, 4, 0, 127, 0, 127);
+                            A0[ai] = load_j(j4rsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
                         }
                     }
-                    // step s + 1 from A1
                     {
                         v4i B[kNBF];
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
-                        const int s_b = s + 2 < nsteps ? s + 2 : s + 1;
+                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
+                        const int s_b = s + 2 < nsteps4 ? s + 2 : s + 1;
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s_b];
-                        const int s_ld = s + 3 < nsteps ? s + 3 : nsteps - 1;
+                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(4 * s_b + g, wlast)];
+                        const int s_ld = s + 3 < nsteps4 ? s + 3 : nsteps4 - 1;
 #pragma unroll
                         for (int ai = 0; ai < 8; ++ai) {
 #pragma unroll
                             for (int f = 0; f < kNBF; ++f)
-                                acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[ai], B[f], acc[ai][f], 0, 0, 0);
-                            A1[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                                accf[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                                    widen(A1[ai]), widen(B[f]), accf[ai][f], 4, 4, 0, 127, 0, 127);
+                            A1[ai] = load_j(j4rsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai)
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[ai][f][j] = (int)accf[ai][f][j];
+            } else {
+                // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
+                // group g ends up with rows 32 g .. 32 g + 31.
+                const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
+                const int bsh = 4 * (g & 1);
+                for (int p = P - 1; p >= 0; --p) {
+                    if (p < P - 1) {
+    #pragma unroll
+                        for (int ai = 0; ai < 8; ++ai)
+    #pragma unroll
+                            for (int f = 0; f < kNBF; ++f) acc[ai][f] = acc[ai][f] * 256;
+                    }
+                    // J is read through a buffer resource (loads past the planes return 0 instead of faulting), one
+                    // contiguous 1 KiB fragment per load.  One A buffer: the loads of step s + 1 are issued right
+                    // behind the MFMAs of step s that read the same registers, so their latency overlaps the rest of
+                    // the MFMA pipeline.
+                    const int voff = lane * 16;
+                    const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
+                    // Two A buffers, loads issued two K steps ahead: buffer b holds step s while the loads of step
+                    // s + 2 refill it right behind the MFMAs that read it.
+                    v4i A0[8], A1[8];
+    #pragma unroll
+                    for (int ai = 0; ai < 8; ++ai) A0[ai] = load_j(jrsrc, voff, tile_off + ai * 1024);
+    #pragma unroll
+                    for (int ai = 0; ai < 8; ++ai) A1[ai] = load_j(jrsrc, voff, tile_off + (8 + ai) * 1024);
+                    uint32_t bw[kNBF];
+    #pragma unroll
+                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
+                    // Drain the first loads here: at the loop head the loads in flight are then exactly the ones the
+                    // previous steps issued in fragment order, so each MFMA group waits for its own fragment only.
+                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                    for (int s = 0; s < nsteps; s += 2) {
+                        // step s from A0 (nsteps is even)
+                        {
+                            v4i B[kNBF];
+    #pragma unroll
+                            for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
+    #pragma unroll
+                            for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * (s + 1)];
+                            const int s_ld = s + 2 < nsteps ? s + 2 : nsteps - 1;
+    #pragma unroll
+                            for (int ai = 0; ai < 8; ++ai) {
+    #pragma unroll
+                                for (int f = 0; f < kNBF; ++f)
+                                    acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0[ai], B[f], acc[ai][f], 0, 0, 0);
+                                A0[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                            }
+                        }
+                        // step s + 1 from A1
+                        {
+                            v4i B[kNBF];
+    #pragma unroll
+                            for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
+                            const int s_b = s + 2 < nsteps ? s + 2 : s + 1;
+    #pragma unroll
+                            for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s_b];
+                            const int s_ld = s + 3 < nsteps ? s + 3 : nsteps - 1;
+    #pragma unroll
+                            for (int ai = 0; ai < 8; ++ai) {
+    #pragma unroll
+                                for (int f = 0; f < kNBF; ++f)
+                                    acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[ai], B[f], acc[ai][f], 0, 0, 0);
+                                A1[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
+                            }
                         }
                     }
                 }
@@ -466,19 +549,19 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     }
 }
 
-template <bool kAlpha1, int kMode, int kNBF>
+template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
 __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
-    sweep_block<kAlpha1, kMode, kNBF>(a, blockIdx.x);
+    sweep_block<kAlpha1, kMode, kNBF, kFp4>(a, blockIdx.x);
 }
 
 // Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
 // host in decreasing cost so that the largest blocks start first.
-template <bool kAlpha1, int kMode, int kNBF>
+template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
 __global__ __launch_bounds__(kThreads, 2) void sweep_batch_kernel(const SweepArgs* __restrict__ items,
                                                                    const uint32_t* __restrict__ work) {
     const uint32_t w = work[blockIdx.x];
     const SweepArgs a = items[w >> 16];
-    sweep_block<kAlpha1, kMode, kNBF>(a, (int)(w & 0xFFFFu));
+    sweep_block<kAlpha1, kMode, kNBF, kFp4>(a, (int)(w & 0xFFFFu));
 }
 
 // int32 J [n][n] -> P balanced int8 planes [P][np][np] (J = sum_p 256^p J_p), zero padded;
@@ -511,6 +594,28 @@ __global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, in
         rowvec[i] = hv;
         rowvec[np + i] = hv - rs;
         rowvec[2 * np + i] = 2 * hv - rs;
+    }
+}
+
+// fp4 (e2m1) code of an integer coupling in {0, +-1, +-2, +-3, +-4, +-6}: magnitude codes 0, 2, 4, 5, 6, 7,
+// sign in bit 3.
+__device__ inline uint32_t fp4_code(int v) {
+    const int m = v < 0 ? -v : v;
+    const uint32_t c = m == 0 ? 0u : m == 1 ? 2u : m == 2 ? 4u : m == 3 ? 5u : m == 4 ? 6u : 7u;
+    return (v < 0 && m != 0) ? (c | 8u) : c;
+}
+
+__global__ void prepare_fp4_kernel(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4) {
+    const int i = blockIdx.x;
+    if (i >= np) return;
+    for (int q = threadIdx.x; q < kp4 / 2; q += blockDim.x) {
+        const int j0 = (q >> 4) * 32 + (q & 15);      // K offset with bit 4 clear; its partner is j0 + 16
+        const int j1 = j0 + 16;
+        const int v0 = (i < n && j0 < n) ? J32[(size_t)i * n + j0] : 0;
+        const int v1 = (i < n && j1 < n) ? J32[(size_t)i * n + j1] : 0;
+        int nib;
+        const size_t off = tiled_offset_fp4(i, j0, kp4, &nib);
+        J4[off] = (uint8_t)(fp4_code(v0) | (fp4_code(v1) << 4));
     }
 }
 
@@ -552,12 +657,57 @@ __global__ void energy_kernel(DeviceProblem prob, const int8_t* spins, int32_t c
     if (threadIdx.x == 0) energies[c] = -red[0] / 2;
 }
 
+// QMC Hamiltonian (Eq. 4) of one trial per workgroup from its counters: sigma = +1 where Is >= 0.
+// H_c = sum_k H_p(sigma_k) - J_perp sum_k sum_i sigma_{i,k} sigma_{i,k+1 mod R}.
+__global__ void qmc_energy_kernel(DeviceProblem prob, const int8_t* counters, int32_t R, int32_t jperp,
+                                  int64_t* out) {
+    const int b = blockIdx.x;
+    const int n = prob.n;
+    const int8_t* trial = counters + (size_t)b * R * n;
+    long long part = 0;   // accumulates -2 H_c
+    for (int k = 0; k < R; ++k) {
+        const int8_t* s = trial + (size_t)k * n;
+        const int8_t* up = trial + (size_t)(k + 1 == R ? 0 : k + 1) * n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int si = s[i] >= 0 ? 1 : -1;
+            long long F = 0;
+            for (int p = prob.planes - 1; p >= 0; --p) {
+                const int8_t* plane = prob.J + (size_t)p * prob.np * prob.np;
+                long long acc = 0;
+                for (int j = 0; j < n; ++j) acc += (int)plane[tiled_offset(i, j, prob.np)] * (s[j] >= 0 ? 1 : -1);
+                F = F * 256 + acc;
+            }
+            part += (long long)si * (2LL * prob.h[i] + F);                 // -2 H_p contribution
+            part += 2LL * jperp * si * (up[i] >= 0 ? 1 : -1);            // -2 (-J_perp sigma sigma_up)
+        }
+    }
+    __shared__ long long red[256];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = -red[0] / 2;
+}
+
 }  // namespace
+
+hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, int32_t trials, int32_t R,
+                             int32_t jperp, int64_t* out, hipStream_t stream) {
+    hipLaunchKernelGGL(qmc_energy_kernel, dim3(trials), dim3(256), 0, stream, prob, counters, R, jperp, out);
+    return hipGetLastError();
+}
 
 size_t sweep_lds_bytes(int np, int delay, int nb) {
     const size_t plane_words = (size_t)nb * (np / 32 + 1);
     return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)nb * 4 * 2 + (size_t)nb * 8 +
            (size_t)nb * 4;
+}
+
+hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4, hipStream_t stream) {
+    hipLaunchKernelGGL(prepare_fp4_kernel, dim3(np), dim3(256), 0, stream, J32, n, np, kp4, J4);
+    return hipGetLastError();
 }
 
 hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
@@ -566,32 +716,38 @@ hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t
     return hipGetLastError();
 }
 
-template <bool kAlpha1, int kMode, int kNBF>
+template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
 hipError_t configure_variant() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode, kNBF>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode, kNBF, kFp4>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kAlpha1, kMode, kNBF>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kAlpha1, kMode, kNBF, kFp4>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     return e;
 }
 
+// Variant v: bit 3 alpha == 1, bit 2 coupling mode 1, bit 1 fp4 operands, bit 0 32 columns per workgroup.
+#define SSQA_FOR_EACH_VARIANT(X) \
+    X(0, false, 0, 4, false) X(1, false, 0, 2, false) X(2, false, 0, 4, true) X(3, false, 0, 2, true) \
+    X(4, false, 1, 4, false) X(5, false, 1, 2, false) X(6, false, 1, 4, true) X(7, false, 1, 2, true) \
+    X(8, true, 0, 4, false) X(9, true, 0, 2, false) X(10, true, 0, 4, true) X(11, true, 0, 2, true) \
+    X(12, true, 1, 4, false) X(13, true, 1, 2, false) X(14, true, 1, 4, true) X(15, true, 1, 2, true)
+
 hipError_t configure_sweep_kernels() {
     static hipError_t status = [] {
-        hipError_t e = configure_variant<true, 0, 4>();
-        if (e == hipSuccess) e = configure_variant<true, 1, 4>();
-        if (e == hipSuccess) e = configure_variant<false, 0, 4>();
-        if (e == hipSuccess) e = configure_variant<false, 1, 4>();
-        if (e == hipSuccess) e = configure_variant<true, 0, 2>();
-        if (e == hipSuccess) e = configure_variant<true, 1, 2>();
-        if (e == hipSuccess) e = configure_variant<false, 0, 2>();
-        if (e == hipSuccess) e = configure_variant<false, 1, 2>();
+        hipError_t e = hipSuccess;
+#define SSQA_CONFIGURE(v, al, mo, nbf, f4) \
+    if (e == hipSuccess) e = configure_variant<al, mo, nbf, f4>();
+        SSQA_FOR_EACH_VARIANT(SSQA_CONFIGURE)
+#undef SSQA_CONFIGURE
         return e;
     }();
     return status;
 }
 
-int sweep_variant(bool alpha1, int mode, int nb) { return (alpha1 ? 4 : 0) + (mode ? 2 : 0) + (nb == 32 ? 1 : 0); }
+int sweep_variant(bool alpha1, int mode, int nb, bool fp4) {
+    return (alpha1 ? 8 : 0) + (mode ? 4 : 0) + (fp4 ? 2 : 0) + (nb == 32 ? 1 : 0);
+}
 
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
                               int variant, hipStream_t stream) {
@@ -599,14 +755,12 @@ hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int 
     const size_t lds = sweep_lds_bytes(max_np, max_delay, nb);
     const dim3 grid(n_work), block(kThreads);
     switch (variant) {
-        case 0: hipLaunchKernelGGL((sweep_batch_kernel<false, 0, 4>), grid, block, lds, stream, items, work); break;
-        case 1: hipLaunchKernelGGL((sweep_batch_kernel<false, 0, 2>), grid, block, lds, stream, items, work); break;
-        case 2: hipLaunchKernelGGL((sweep_batch_kernel<false, 1, 4>), grid, block, lds, stream, items, work); break;
-        case 3: hipLaunchKernelGGL((sweep_batch_kernel<false, 1, 2>), grid, block, lds, stream, items, work); break;
-        case 4: hipLaunchKernelGGL((sweep_batch_kernel<true, 0, 4>), grid, block, lds, stream, items, work); break;
-        case 5: hipLaunchKernelGGL((sweep_batch_kernel<true, 0, 2>), grid, block, lds, stream, items, work); break;
-        case 6: hipLaunchKernelGGL((sweep_batch_kernel<true, 1, 4>), grid, block, lds, stream, items, work); break;
-        case 7: hipLaunchKernelGGL((sweep_batch_kernel<true, 1, 2>), grid, block, lds, stream, items, work); break;
+#define SSQA_LAUNCH_BATCH(v, al, mo, nbf, f4)                                                                \
+    case v:                                                                                                \
+        hipLaunchKernelGGL((sweep_batch_kernel<al, mo, nbf, f4>), grid, block, lds, stream, items, work); \
+        break;
+        SSQA_FOR_EACH_VARIANT(SSQA_LAUNCH_BATCH)
+#undef SSQA_LAUNCH_BATCH
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -617,15 +771,13 @@ hipError_t launch_sweep(const SweepArgs& a, int n_wg, hipStream_t stream) {
     if (ce != hipSuccess) return ce;
     const size_t lds = sweep_lds_bytes(a.prob.np, a.delay, a.nb);
     const dim3 grid(n_wg), block(kThreads);
-    switch (sweep_variant(a.alpha == 1, a.mode, a.nb)) {
-        case 0: hipLaunchKernelGGL((sweep_kernel<false, 0, 4>), grid, block, lds, stream, a); break;
-        case 1: hipLaunchKernelGGL((sweep_kernel<false, 0, 2>), grid, block, lds, stream, a); break;
-        case 2: hipLaunchKernelGGL((sweep_kernel<false, 1, 4>), grid, block, lds, stream, a); break;
-        case 3: hipLaunchKernelGGL((sweep_kernel<false, 1, 2>), grid, block, lds, stream, a); break;
-        case 4: hipLaunchKernelGGL((sweep_kernel<true, 0, 4>), grid, block, lds, stream, a); break;
-        case 5: hipLaunchKernelGGL((sweep_kernel<true, 0, 2>), grid, block, lds, stream, a); break;
-        case 6: hipLaunchKernelGGL((sweep_kernel<true, 1, 4>), grid, block, lds, stream, a); break;
-        case 7: hipLaunchKernelGGL((sweep_kernel<true, 1, 2>), grid, block, lds, stream, a); break;
+    switch (sweep_variant(a.alpha == 1, a.mode, a.nb, a.fp4 != 0)) {
+#define SSQA_LAUNCH_ONE(v, al, mo, nbf, f4)                                                \
+    case v:                                                                              \
+        hipLaunchKernelGGL((sweep_kernel<al, mo, nbf, f4>), grid, block, lds, stream, a); \
+        break;
+        SSQA_FOR_EACH_VARIANT(SSQA_LAUNCH_ONE)
+#undef SSQA_LAUNCH_ONE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -205,3 +205,52 @@ def test_large_n_uses_narrow_blocks(lib):
     gpu = run_gpu(prob, trials=10, **kw)
     ref = run_oracle(h, J, trials=[0, 9], **kw)
     assert_same(gpu, ref, trial_idx=[0, 9])
+
+
+def test_qmc_energy_entry_point(lib):
+    """H_c (Eq. 4) of the final state of an anneal against the oracle's qmc_energy."""
+    _note("case ssqa_qmc_energy")
+    h, J, e_star = gi_case(7, 8)
+    q, i0, noise = paper_schedules(80, tau=10)
+    prob = lib.Problem(h, J)
+    res = lib.ssqa_anneal(prob, replicas=6, trials=9, cycles=80, jperp=q, i0=i0, alpha=1, noise_amp=noise,
+                          delay=1, seed=4, final_is=True)
+    hc = lib.ssqa_qmc_energy(prob, res.final_is, jperp=6).cpu().numpy()
+    sigma = np.where(res.final_is.cpu().numpy() >= 0, 1, -1).astype(np.int64)
+    assert np.array_equal(hc, ssqa.qmc_energy(h, J, sigma, 6))
+
+
+@pytest.mark.parametrize("case", ["gi9", "ising300", "ising129_mode1_d0", "ising_tail"])
+def test_fp4_operands_equal_int8_and_oracle(lib, case):
+    """When every J_ij is exactly representable in fp4 (e2m1), the fp4 field product (fp32 accumulation)
+    gives exactly the int8 results and the oracle's."""
+    _note(f"case fp4 vs int8 {case}")
+    if case == "gi9":
+        h, J, e_star = gi_case(9, 6)
+        q, i0, noise = paper_schedules(120, tau=10)
+        kw = dict(replicas=16, trials=12, cycles=120, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=9,
+                  target=e_star)
+    else:
+        n, mode, d = {"ising300": (300, 0, 1), "ising129_mode1_d0": (129, 1, 0), "ising_tail": (385, 0, 2)}[case]
+        h, J = random_ising(n, n, h_max=50, j_max=4)
+        J[J == 5] = 6
+        J[J == -5] = -6
+        rng = np.random.default_rng(n)
+        q = rng.integers(0, 9, size=40)
+        i0 = rng.integers(5, 90, size=40)
+        kw = dict(replicas=5, trials=14, cycles=40, q=q, i0=i0, alpha=2, noise=9, delay=d, seed=n, mode=mode)
+    prob = lib.Problem(h, J)
+    f4 = run_gpu(prob, operand_format=2, **kw)
+    i8 = run_gpu(prob, operand_format=1, **kw)
+    for key in ("best", "first_hit", "trace", "Is"):
+        assert np.array_equal(f4[key], i8[key]), key
+    assert_same(f4, run_oracle(h, J, **kw))
+
+
+def test_fp4_refused_when_inexact(lib):
+    h, J = random_ising(40, 3, h_max=20, j_max=9)
+    prob = lib.Problem(h, J)
+    with pytest.raises(lib.SSQAError) as ei:
+        run_gpu(prob, replicas=2, trials=2, cycles=3, q=[0, 0, 0], i0=[9, 9, 9], alpha=1, noise=1, delay=1, seed=0,
+                operand_format=2)
+    assert ei.value.name == "SSQA_ENOTSUP"
