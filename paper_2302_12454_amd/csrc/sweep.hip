@@ -86,6 +86,76 @@ __device__ __forceinline__ v4i load_j(__amdgpu_buffer_rsrc_t rsrc, int voffset, 
 __device__ __forceinline__ int bfe_i(int w, int off, int width) { return __builtin_amdgcn_sbfe(w, off, width); }
 __device__ __forceinline__ uint32_t bfe_u(uint32_t w, int off, int width) { return __builtin_amdgcn_ubfe(w, off, width); }
 
+// The 8 A fragments (one K step of a 128-row tile) at byte offset `off` of the J buffer.
+__device__ __forceinline__ void load_fragments(v4i (&A)[8], __amdgpu_buffer_rsrc_t rsrc, int voff, int off) {
+#pragma unroll
+    for (int ai = 0; ai < 8; ++ai) A[ai] = load_j(rsrc, voff, off + ai * 1024);
+}
+
+// One K step on int8 operands: acc[ai][f] += A[ai] . B[f]; with kReload, A[ai] is refilled from byte offset
+// `next` right behind the MFMAs that read it.
+template <int kNBF, bool kReload>
+__device__ __forceinline__ void mma_i8(v4i (&A)[8], const v4i (&B)[kNBF], v4i (&acc)[8][kNBF],
+                                       __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
+#pragma unroll
+    for (int ai = 0; ai < 8; ++ai) {
+#pragma unroll
+        for (int f = 0; f < kNBF; ++f) acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], B[f], acc[ai][f], 0, 0, 0);
+        if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+    }
+}
+
+// One K step on fp4 (e2m1) operands, both scales 2^0, fp32 accumulation.
+template <int kNBF, bool kReload>
+__device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (&acc)[8][kNBF],
+                                        __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
+#pragma unroll
+    for (int ai = 0; ai < 8; ++ai) {
+#pragma unroll
+        for (int f = 0; f < kNBF; ++f)
+            acc[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(widen(A[ai]), widen(B[f]), acc[ai][f], 4, 4,
+                                                                          0, 127, 0, 127);
+        if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+    }
+}
+
+// The 32 int8 counters of this lane in column fragment f (column 16 f + lane % 16); they are touched once
+// per cycle, so they stream past the cache that holds J.
+__device__ __forceinline__ void load_counters(v4i (&c)[2], const int8_t* is_lane, int np, int f) {
+    const v4i* src = reinterpret_cast<const v4i*>(is_lane + (size_t)16 * f * np);
+    c[0] = __builtin_nontemporal_load(src);
+    c[1] = __builtin_nontemporal_load(src + 1);
+}
+
+// Counters are fetched kCntAhead fragments ahead of their use: those of fragments 0 .. kCntAhead - 1 during
+// the last K steps, that of fragment f + kCntAhead while the epilogue works on fragment f.
+constexpr int kCntAhead = 1;
+
+template <int kNBF>
+__device__ __forceinline__ void prefetch_counters(v4i (&cnt)[kNBF][2], const int8_t* is_lane, int np) {
+#pragma unroll
+    for (int f = 0; f < kNBF && f < kCntAhead; ++f) load_counters(cnt[f], is_lane, np, f);
+}
+
+// 4 rows of the tile's row vectors: lane l < 32 takes h - rowsum at rows 4 l .. 4 l + 3, lane l >= 32 takes
+// 2 h - rowsum at rows 4 (l - 32) .. 4 (l - 32) + 3.
+__device__ __forceinline__ v4i fetch_rows(const DeviceProblem& prob, int tile) {
+    int ln = threadIdx.x & 63;
+    asm volatile("" : "+v"(ln));
+    return *reinterpret_cast<const v4i*>((ln < 32 ? prob.hr : prob.er) + tile * kTileRows + 4 * (ln & 31));
+}
+
+// Writes the row vectors fetched by this lane into the wave's staging area; h - rowsum gets the cycle's
+// constant offset added.  The lane index is laundered so that no per-lane select is hoisted out of the tile
+// loop into registers.
+__device__ __forceinline__ void stage_rows(int32_t* st, v4i rowv, int adj) {
+    int ln = threadIdx.x & 63;
+    asm volatile("" : "+v"(ln));
+    const int add = ln < 32 ? adj : 0;
+    rowv += add;
+    *reinterpret_cast<v4i*>(st + 4 * ln) = rowv;
+}
+
 struct EpilogueCtx {
     const uint32_t* pl_cur;   // sigma(t) bit plane
     const uint32_t* pl_del;   // sigma(t - d) bit plane
@@ -94,8 +164,7 @@ struct EpilogueCtx {
     const uint32_t* colinfo;
     int32_t* e_acc;
     int8_t* is_wg;
-    const int32_t* hr;
-    const int32_t* er;
+    const int32_t* rows;      // this wave's staged row vectors: [0, 128) h - rowsum + adj, [128, 256) 2 h - rowsum
     int np, cstride, tile, wave, lane;
     int adj, two_n, two_q, i0, alpha;
 };
@@ -119,7 +188,8 @@ __device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
 // counters and the next bit plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the
 // current state is always accumulated.
 template <bool kUpdate, bool kAlpha1, int kMode, int kNBF>
-__device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const EpilogueCtx& x) {
+__device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&cnt)[kNBF][2],
+                                               const EpilogueCtx& x) {
     // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live (in
     // registers) across the K loop.
     int ln = x.lane;
@@ -137,21 +207,20 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const 
         const uint32_t nsig = ~x.pl_cur[c * x.cstride + word];
         int ep = __builtin_popcount(nsig);
         uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
-        v4i is_lo, is_hi;
         v4i* is_ptr = reinterpret_cast<v4i*>(x.is_wg + (size_t)c * x.np + row0);
+        if (kUpdate && f + kCntAhead < kNBF)
+            load_counters(cnt[f + kCntAhead], x.is_wg + (size_t)ecol * x.np + row0, x.np, f + kCntAhead);
+        v4i is_lo = cnt[f][0], is_hi = cnt[f][1];
         if (kUpdate) {
             up_w = x.pl_del[(info & 0xFFu) * x.cstride + word];
             if (kMode == 1) dn_w = x.pl_del[((info >> 8) & 0xFFu) * x.cstride + word];
             noise_w = x.noise_lds[(x.wave * 64 + c) * 4 + eg];
-            // counters are touched once per cycle: stream them past the cache that holds J
-            is_lo = __builtin_nontemporal_load(is_ptr);
-            is_hi = __builtin_nontemporal_load(is_ptr + 1);
         }
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
-            const v4i er4 = *reinterpret_cast<const v4i*>(x.er + row0 + 4 * ai);
+            const v4i er4 = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
             v4i hq4;
-            if (kUpdate) hq4 = *reinterpret_cast<const v4i*>(x.hr + row0 + 4 * ai) + x.adj;
+            if (kUpdate) hq4 = *reinterpret_cast<const v4i*>(x.rows + 32 * eg + 4 * ai);
             // bit position of row offset 4 ai + j is 8 j + cpos
             const int cpos = 4 * (ai >> 2) + (ai & 3);
             uint32_t isw_new = 0;
@@ -200,6 +269,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], const 
 //   hit     [kNB]   int32               per-trial first hit
 //   best    [kNB]   int64               per-trial best energy
 //   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
+//   rows    [kWaves][256] int32         row vectors of each wave's current tile
 // All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
 template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
@@ -215,6 +285,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     int32_t* hit_l = e_acc + kNB;
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
     uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
+    int32_t* rowst = reinterpret_cast<int32_t*>(colinfo + kNB);      // [kWaves][256]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -327,11 +398,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 
         for (int tile = wave; tile < ntiles; tile += kWaves) {
             v4i acc[8][kNBF];
-#pragma unroll
-            for (int ai = 0; ai < 8; ++ai)
-#pragma unroll
-                for (int f = 0; f < kNBF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
-
+            // Fetched during the last K steps, for the epilogue: this lane's counters of the tile, and 4 rows
+            // of a row vector of the tile (lane l < 32: h - rowsum, lane l >= 32: 2 h - rowsum).
+            v4i cnt[kNBF][2];
+            v4i rowv;
+            int8_t* is_lane = is_wg + (size_t)col16 * np + tile * kTileRows + 32 * g;
+            const int voff = lane * 16;
             if constexpr (kFp4) {
                 // Field product on the fp4 copy of J: K steps of 128, fp32 accumulators (exact: every partial
                 // sum is an integer far below 2^24), converted to int for the epilogue.
@@ -340,54 +412,45 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
                     for (int f = 0; f < kNBF; ++f) accf[ai][f] = v4f{0.f, 0.f, 0.f, 0.f};
-                const int nsteps4 = a.prob.kp4 / 128;          // even
+                const int ns = a.prob.kp4 / 128;          // even, >= 2
                 const uint32_t* bsrc = pl_cur + col16 * cstride;
                 const int wlast = words - 1;
-                const int voff = lane * 16;
-                const int tile_off = tile * nsteps4 * 8 * 1024;
+                const int tile_off = tile * ns * 8 * 1024;
                 v4i A0[8], A1[8];
-#pragma unroll
-                for (int ai = 0; ai < 8; ++ai) A0[ai] = load_j(j4rsrc, voff, tile_off + ai * 1024);
-#pragma unroll
-                for (int ai = 0; ai < 8; ++ai) A1[ai] = load_j(j4rsrc, voff, tile_off + (8 + ai) * 1024);
                 uint32_t bw[kNBF];
+                load_fragments(A0, j4rsrc, voff, tile_off);
+                load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
 #pragma unroll
                 for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(g, wlast)];
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
-                for (int s = 0; s < nsteps4; s += 2) {
-                    {
-                        v4i B[kNBF];
+                auto next_b = [&](int s) {
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
+                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(4 * s + g, wlast)];
+                };
+                auto expand = [&](v4i (&B)[kNBF]) {
 #pragma unroll
-                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(4 * (s + 1) + g, wlast)];
-                        const int s_ld = s + 2 < nsteps4 ? s + 2 : nsteps4 - 1;
-#pragma unroll
-                        for (int ai = 0; ai < 8; ++ai) {
-#pragma unroll
-                            for (int f = 0; f < kNBF; ++f)
-                                accf[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                                    widen(A0[ai]), widen(B[f]), accf[ai][f], 4, 4, 0, 127, 0, 127);
-                            A0[ai] = load_j(j4rsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
-                        }
-                    }
-                    {
-                        v4i B[kNBF];
-#pragma unroll
-                        for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
-                        const int s_b = s + 2 < nsteps4 ? s + 2 : s + 1;
-#pragma unroll
-                        for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(4 * s_b + g, wlast)];
-                        const int s_ld = s + 3 < nsteps4 ? s + 3 : nsteps4 - 1;
-#pragma unroll
-                        for (int ai = 0; ai < 8; ++ai) {
-#pragma unroll
-                            for (int f = 0; f < kNBF; ++f)
-                                accf[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                                    widen(A1[ai]), widen(B[f]), accf[ai][f], 4, 4, 0, 127, 0, 127);
-                            A1[ai] = load_j(j4rsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
-                        }
-                    }
+                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
+                };
+                // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
+                for (int s = 0; s < ns - 2; s += 2) {
+                    v4i B[kNBF];
+                    expand(B);
+                    next_b(s + 1);
+                    mma_fp4<kNBF, true>(A0, B, accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
+                    expand(B);
+                    next_b(s + 2);
+                    mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
+                }
+                {
+                    // The last two steps: no J left to fetch; the epilogue's counters are fetched instead.
+                    v4i B[kNBF];
+                    expand(B);
+                    next_b(ns - 1);
+                    mma_fp4<kNBF, false>(A0, B, accf, j4rsrc, voff, 0);
+                    rowv = fetch_rows(a.prob, tile);
+                    prefetch_counters(cnt, is_lane, np);
+                    expand(B);
+                    mma_fp4<kNBF, false>(A1, B, accf, j4rsrc, voff, 0);
                 }
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
@@ -396,70 +459,61 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                         for (int j = 0; j < 4; ++j) acc[ai][f][j] = (int)accf[ai][f][j];
             } else {
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai)
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
                 // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
                 // group g ends up with rows 32 g .. 32 g + 31.
                 const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
                 const int bsh = 4 * (g & 1);
+                uint32_t bw[kNBF];
+                auto next_b = [&](int s) {
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s];
+                };
+                auto expand = [&](v4i (&B)[kNBF]) {
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
+                };
                 for (int p = P - 1; p >= 0; --p) {
                     if (p < P - 1) {
-    #pragma unroll
+#pragma unroll
                         for (int ai = 0; ai < 8; ++ai)
-    #pragma unroll
+#pragma unroll
                             for (int f = 0; f < kNBF; ++f) acc[ai][f] = acc[ai][f] * 256;
                     }
-                    // J is read through a buffer resource (loads past the planes return 0 instead of faulting), one
-                    // contiguous 1 KiB fragment per load.  One A buffer: the loads of step s + 1 are issued right
-                    // behind the MFMAs of step s that read the same registers, so their latency overlaps the rest of
-                    // the MFMA pipeline.
-                    const int voff = lane * 16;
+                    // J is read through a buffer resource (loads past the planes return 0 instead of faulting),
+                    // one contiguous 1 KiB fragment per load, into two A buffers: buffer b holds step s while the
+                    // loads of step s + 2 refill it right behind the MFMAs that read it.
                     const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
-                    // Two A buffers, loads issued two K steps ahead: buffer b holds step s while the loads of step
-                    // s + 2 refill it right behind the MFMAs that read it.
                     v4i A0[8], A1[8];
-    #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai) A0[ai] = load_j(jrsrc, voff, tile_off + ai * 1024);
-    #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai) A1[ai] = load_j(jrsrc, voff, tile_off + (8 + ai) * 1024);
-                    uint32_t bw[kNBF];
-    #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
-                    // Drain the first loads here: at the loop head the loads in flight are then exactly the ones the
-                    // previous steps issued in fragment order, so each MFMA group waits for its own fragment only.
+                    load_fragments(A0, jrsrc, voff, tile_off);
+                    load_fragments(A1, jrsrc, voff, tile_off + 8 * 1024);
+                    next_b(0);
+                    // Drain the first loads here: at the loop head the loads in flight are then exactly the ones
+                    // the previous steps issued in fragment order, so each MFMA group waits for its own fragment.
                     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-                    for (int s = 0; s < nsteps; s += 2) {
-                        // step s from A0 (nsteps is even)
-                        {
-                            v4i B[kNBF];
-    #pragma unroll
-                            for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
-    #pragma unroll
-                            for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * (s + 1)];
-                            const int s_ld = s + 2 < nsteps ? s + 2 : nsteps - 1;
-    #pragma unroll
-                            for (int ai = 0; ai < 8; ++ai) {
-    #pragma unroll
-                                for (int f = 0; f < kNBF; ++f)
-                                    acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0[ai], B[f], acc[ai][f], 0, 0, 0);
-                                A0[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
-                            }
+                    for (int s = 0; s < nsteps - 2; s += 2) {
+                        v4i B[kNBF];
+                        expand(B);
+                        next_b(s + 1);
+                        mma_i8<kNBF, true>(A0, B, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
+                        expand(B);
+                        next_b(s + 2);
+                        mma_i8<kNBF, true>(A1, B, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
+                    }
+                    {
+                        v4i B[kNBF];
+                        expand(B);
+                        next_b(nsteps - 1);
+                        mma_i8<kNBF, false>(A0, B, acc, jrsrc, voff, 0);
+                        if (p == 0) {
+                            rowv = fetch_rows(a.prob, tile);
+                            prefetch_counters(cnt, is_lane, np);
                         }
-                        // step s + 1 from A1
-                        {
-                            v4i B[kNBF];
-    #pragma unroll
-                            for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
-                            const int s_b = s + 2 < nsteps ? s + 2 : s + 1;
-    #pragma unroll
-                            for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s_b];
-                            const int s_ld = s + 3 < nsteps ? s + 3 : nsteps - 1;
-    #pragma unroll
-                            for (int ai = 0; ai < 8; ++ai) {
-    #pragma unroll
-                                for (int f = 0; f < kNBF; ++f)
-                                    acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1[ai], B[f], acc[ai][f], 0, 0, 0);
-                                A1[ai] = load_j(jrsrc, voff, tile_off + (s_ld * 8 + ai) * 1024);
-                            }
-                        }
+                        expand(B);
+                        mma_i8<kNBF, false>(A1, B, acc, jrsrc, voff, 0);
                     }
                 }
             }
@@ -473,8 +527,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             ctx.colinfo = colinfo;
             ctx.e_acc = e_acc;
             ctx.is_wg = is_wg;
-            ctx.hr = a.prob.hr;
-            ctx.er = a.prob.er;
+            ctx.rows = rowst + wave * 256;
+            stage_rows(rowst + wave * 256, rowv, adj);
             ctx.np = np;
             ctx.cstride = cstride;
             ctx.tile = tile;
@@ -498,9 +552,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                fused_epilogue<true, kAlpha1, kMode, kNBF>(acc, ctx);
+                fused_epilogue<true, kAlpha1, kMode, kNBF>(acc, cnt, ctx);
             } else {
-                fused_epilogue<false, kAlpha1, kMode, kNBF>(acc, ctx);
+                fused_epilogue<false, kAlpha1, kMode, kNBF>(acc, cnt, ctx);
             }
         }
         __syncthreads();
@@ -702,7 +756,7 @@ hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, 
 size_t sweep_lds_bytes(int np, int delay, int nb) {
     const size_t plane_words = (size_t)nb * (np / 32 + 1);
     return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)nb * 4 * 2 + (size_t)nb * 8 +
-           (size_t)nb * 4;
+           (size_t)nb * 4 + (size_t)kWaves * 256 * 4;
 }
 
 hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4, hipStream_t stream) {
