@@ -67,7 +67,7 @@ typedef struct ssqa_problem* ssqa_problem_t;
  *   out     : receives the handle.
  * J is stored as P signed int8 planes with J = sum_p 256^p J_p (P = 1 when every |J_ij| <= 127),
  * zero-padded to a multiple of 128 rows and columns, and additionally as fp4 (e2m1) when every J_ij is
- * one of 0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J_ij| is below 2^24 (then the fp4 field
+ * one of 0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J_ij| is below 2^21 (then the fp4 field
  * product with fp32 accumulation is exact).
  * Fails with SSQA_EINVAL for a bad size, pointer or non-symmetric J, and with SSQA_ERANGE when
  * 2 * sum_i |h_i| + sum_ij |J_ij| >= 2^30 (energies and fields must stay inside int32).
@@ -111,7 +111,7 @@ typedef struct ssqa_anneal_params {
                                   and the bit planes fit in LDS, else 32), or 32 / 64.  A tiling
                                   choice only: results do not depend on it                        */
     int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when every J_ij is one of
-                                  0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J| is below 2^24,
+                                  0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J| is below 2^21,
                                   else int8 planes); 1 = int8 planes; 2 = fp4 (e2m1, fp32
                                   accumulation, exact under the same conditions; SSQA_ENOTSUP
                                   otherwise).  Results do not depend on it                         */

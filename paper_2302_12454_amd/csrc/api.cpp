@@ -72,6 +72,21 @@ bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
     return prob->dev.J4 != nullptr;
 }
 
+// The byte-parallel counter update applies when alpha = 1 and every counter plus 128 plus its noise and
+// coupling increments stays below 256.  A counter holds at most max_t I0(t) - 1 (it may have been clamped
+// in an earlier cycle with a larger I0), so the bound is taken over the whole schedule:
+// max_t I0(t) + 2 noise_amp + 2 max_t |jperp(t)| (1 + mode) <= 128.
+bool fast_epilogue(const ssqa_anneal_params* pa) {
+    if (pa->alpha != 1) return false;
+    long long i0_max = 1, q_max = 0;
+    for (int t = 0; t < pa->cycles; ++t) {
+        const long long q = pa->jperp[t] < 0 ? -(long long)pa->jperp[t] : pa->jperp[t];
+        i0_max = std::max<long long>(i0_max, pa->i0[t]);
+        q_max = std::max(q_max, q);
+    }
+    return i0_max + 2LL * pa->noise_amp + 2 * q_max * (1 + pa->coupling_mode) <= 128;
+}
+
 // Columns per workgroup: the requested width, or 64 when R <= 64 and the bit planes fit in LDS, else 32.
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
     if (pa->block_columns == 32 || pa->block_columns == 64) return pa->block_columns;
@@ -117,6 +132,7 @@ SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, cons
     a.prob = prob->dev;
     a.nb = nb;
     a.fp4 = use_fp4(prob, pa) ? 1 : 0;
+    a.fast = fast_epilogue(pa) ? 1 : 0;
     a.R = pa->replicas;
     a.T = pa->trials;
     a.tpw = tpw;
@@ -177,7 +193,7 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     if (!h || !J) return fail(SSQA_EINVAL, "h or J is NULL");
     long long total = 0;
     int planes = 1;
-    bool fp4_exact = true;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6} and every row sum of |J| < 2^24
+    bool fp4_exact = true;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6} and every row sum of |J| < 2^21
     for (int i = 0; i < n; ++i) {
         total += 2LL * std::llabs((long long)h[i]);
         long long row_abs = 0;
@@ -192,7 +208,7 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
             const int m = v < 0 ? -v : v;
             if (m > 6 || m == 5) fp4_exact = false;
         }
-        if (row_abs >= (1LL << 24)) fp4_exact = false;
+        if (row_abs >= (1LL << 21)) fp4_exact = false;
         if (total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
     }
     int dev_count = 0;
@@ -389,7 +405,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         items[i].t_end = SC;
         items[i].final_pass = 1;
         io += (size_t)n_wg[i] * nbs[i] * problems[i]->dev.np;
-        const int v = sweep_variant(pa.alpha == 1, pa.coupling_mode, nbs[i], items[i].fp4 != 0);
+        const int v = sweep_variant(items[i].fast != 0, pa.coupling_mode, nbs[i], items[i].fp4 != 0);
         const double np = problems[i]->dev.np;
         const double cost = np * np * problems[i]->dev.planes * (SC + 1.0);
         for (int c = 0; c < n_wg[i]; ++c) lists[v].push_back({cost, ((uint32_t)i << 16) | (uint32_t)c});

@@ -62,6 +62,7 @@ struct SweepArgs {
     DeviceProblem prob;
     int32_t nb;             // columns per workgroup: 64 or 32
     int32_t fp4;            // 1: the field product runs on the fp4 copy of J
+    int32_t fast;           // 1: alpha = 1 and max I0 + 2 noise_amp + 2 max |jperp| (1 + mode) <= 128
     int32_t R;              // replicas
     int32_t T;              // trials
     int32_t tpw;            // trials per workgroup
@@ -96,7 +97,7 @@ hipError_t configure_sweep_kernels();
 size_t sweep_lds_bytes(int np, int delay, int nb);
 // Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.
 constexpr int kSweepVariants = 16;
-int sweep_variant(bool alpha1, int mode, int nb, bool fp4);
+int sweep_variant(bool fast, int mode, int nb, bool fp4);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
 // items: device array of anneals; work: device list of (item << 16 | column block), n_work entries, all of
 // one kernel variant; the LDS size is taken for the largest padded N and delay among them.

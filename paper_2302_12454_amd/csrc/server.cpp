@@ -266,7 +266,7 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
         a.final_pass = a.t_end == r->params.cycles ? 1 : 0;
         s->items[i] = a;
         updates += (double)r->n * r->params.replicas * r->params.trials * (a.t_end - a.t_begin);
-        const int v = sweep_variant(a.alpha == 1, a.mode, a.nb, a.fp4 != 0);
+        const int v = sweep_variant(a.fast != 0, a.mode, a.nb, a.fp4 != 0);
         const double np = a.prob.np;
         const double cost = np * np * a.prob.planes * (a.t_end - a.t_begin + 1);
         for (int c = 0; c < r->n_wg; ++c) lists[v].push_back({cost, ((uint32_t)i << 16) | (uint32_t)c});

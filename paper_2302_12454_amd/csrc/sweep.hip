@@ -105,7 +105,7 @@ __device__ __forceinline__ void mma_i8(v4i (&A)[8], const v4i (&B)[kNBF], v4i (&
     }
 }
 
-// One K step on fp4 (e2m1) operands, both scales 2^0, fp32 accumulation.
+// One K step on fp4 (e2m1) operands, fp32 accumulation; J is scaled by 2 (e8m0 scale 128), x by 1.
 template <int kNBF, bool kReload>
 __device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (&acc)[8][kNBF],
                                         __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
@@ -114,7 +114,7 @@ __device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (
 #pragma unroll
         for (int f = 0; f < kNBF; ++f)
             acc[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(widen(A[ai]), widen(B[f]), acc[ai][f], 4, 4,
-                                                                          0, 127, 0, 127);
+                                                                          0, 128, 0, 127);
         if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
     }
 }
@@ -145,13 +145,12 @@ __device__ __forceinline__ v4i fetch_rows(const DeviceProblem& prob, int tile) {
     return *reinterpret_cast<const v4i*>((ln < 32 ? prob.hr : prob.er) + tile * kTileRows + 4 * (ln & 31));
 }
 
-// Writes the row vectors fetched by this lane into the wave's staging area; h - rowsum gets the cycle's
-// constant offset added.  The lane index is laundered so that no per-lane select is hoisted out of the tile
-// loop into registers.
-__device__ __forceinline__ void stage_rows(int32_t* st, v4i rowv, int adj) {
+// Writes the row vectors fetched by this lane into the wave's staging area, each plus its cycle constant.
+// The lane index is laundered so that no per-lane select is hoisted out of the tile loop into registers.
+__device__ __forceinline__ void stage_rows(int32_t* st, v4i rowv, int add_h, int add_e) {
     int ln = threadIdx.x & 63;
     asm volatile("" : "+v"(ln));
-    const int add = ln < 32 ? adj : 0;
+    const int add = ln < 32 ? add_h : add_e;
     rowv += add;
     *reinterpret_cast<v4i*>(st + 4 * ln) = rowv;
 }
@@ -164,10 +163,19 @@ struct EpilogueCtx {
     const uint32_t* colinfo;
     int32_t* e_acc;
     int8_t* is_wg;
-    const int32_t* rows;      // this wave's staged row vectors: [0, 128) h - rowsum + adj, [128, 256) 2 h - rowsum
+    // This wave's staged row constants: [0, 128) the per-row part of the counter input, [128, 256) the
+    // per-row part of the energy term (see sweep_block for what each holds).
+    const int32_t* rows;
     int np, cstride, tile, wave, lane;
-    int adj, two_n, two_q, i0, alpha;
+    int two_n, two_q, i0, alpha;
+    uint32_t qflip;           // fast path: 0, or all ones when J_perp < 0 (the coupling bits are complemented)
 };
+
+__device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
 
 // v_perm_b32 selectors that put byte 0 of the second operand at byte j and keep the other bytes of the first.
 __host__ __device__ constexpr uint32_t insert_byte_sel(int j) {
@@ -176,18 +184,39 @@ __host__ __device__ constexpr uint32_t insert_byte_sel(int j) {
     return sel;
 }
 
-__device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
+// (a ^ b) + c in one instruction.
+__device__ __forceinline__ int xad_u32(int a, int b, int c) {
     int r;
-    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    asm("v_xad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Bits 4 a .. 4 a + 3 of w, one per byte (bit 4 a + j -> bit 8 j).
+__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t w, int a) {
+    return (bfe_u(w, 4 * a, 4) * 0x00204081u) & 0x01010101u;
+}
+
+// Twice the field part of the counter input, 2 sum_j J_ij x_j, plus the accumulator's constant offset.
+template <bool kFp4>
+__device__ __forceinline__ int field2(int acc) { return kFp4 ? acc : acc * 2; }
 
 // Fused epilogue of one 128-row tile for the kNBF column fragments of this wave.  Lane (column
 // 16 f + (lane & 15), group g = lane >> 4) owns tile rows 32 g .. 32 g + 31 of fragment f, i.e. one 32-bit
 // word of every bit plane and of the Philox block, and 32 consecutive int8 counters.  With kUpdate the
 // counters and the next bit plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the
 // current state is always accumulated.
-template <bool kUpdate, bool kAlpha1, int kMode, int kNBF>
+//
+// Row offset o = 4 a + j of the lane's 32 rows sits in byte j of counter dword a and at bit 8 j + a of the
+// bit-plane words (bitpos), and at bit o of the Philox word.
+//
+// kFast (alpha = 1, and max_t I_0 + 2 n_rnd + 2 max_t |J_perp| (1 + mode) <= 128): the counters of the 4
+// rows of dword a, offset by 128, and their noise and coupling increments 2 n_rnd [r = +1] and
+// 2 |J_perp| [coupled spin agrees with the sign of J_perp] are summed as 4 bytes at once without carries;
+// per row only the field is added and the sum clamped to [-I_0, I_0 - 1] (Eq. 6b with alpha = 1).
+// Otherwise each row's input is assembled in 32 bits and clamped as Eq. 6b states for any alpha.
+template <bool kUpdate, bool kFast, int kMode, int kNBF, bool kFp4>
 __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&cnt)[kNBF][2],
                                                const EpilogueCtx& x) {
     // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live (in
@@ -199,6 +228,8 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
     const int word = x.tile * 4 + eg;
     const int row0 = x.tile * kTileRows + 32 * eg;
     const int lo = -x.i0, hi = x.i0 - 1;
+    const uint32_t tn2 = (uint32_t)x.two_n * 0x00010001u;
+    const uint32_t tq2 = (uint32_t)x.two_q * 0x00010001u;
 
 #pragma unroll
     for (int f = 0; f < kNBF; ++f) {
@@ -215,39 +246,48 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
             up_w = x.pl_del[(info & 0xFFu) * x.cstride + word];
             if (kMode == 1) dn_w = x.pl_del[((info >> 8) & 0xFFu) * x.cstride + word];
             noise_w = x.noise_lds[(x.wave * 64 + c) * 4 + eg];
+            if (kFast) {
+                up_w ^= x.qflip;
+                dn_w ^= x.qflip;
+            }
         }
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
             const v4i er4 = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
             v4i hq4;
             if (kUpdate) hq4 = *reinterpret_cast<const v4i*>(x.rows + 32 * eg + 4 * ai);
-            // bit position of row offset 4 ai + j is 8 j + cpos
-            const int cpos = 4 * (ai >> 2) + (ai & 3);
             uint32_t isw_new = 0;
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
+            uint32_t s4 = 0;
+            if (kUpdate && kFast) {
+                uint32_t c4 = (up_w >> ai) & 0x01010101u;
+                if (kMode == 1) c4 += (dn_w >> ai) & 0x01010101u;
+                const u16x2 t = __builtin_bit_cast(u16x2, nibble_to_bytes(noise_w, ai)) * __builtin_bit_cast(u16x2, tn2) +
+                                __builtin_bit_cast(u16x2, c4) * __builtin_bit_cast(u16x2, tq2);
+                s4 = (uint32_t)xad_u32(isw, (int)0x80808080u, (int)__builtin_bit_cast(uint32_t, t));
+            }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int o = 4 * ai + j;
-                const int pos = 8 * j + cpos;
-                const int accv = acc[ai][f][j];
+                const int pos = 8 * j + ai;
+                const int f2 = field2<kFp4>(acc[ai][f][j]);
                 // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
-                ep += ((accv << 1) + er4[j]) ^ bfe_i((int)nsig, pos, 1);
+                ep = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep);
                 if (kUpdate) {
-                    int t = (bfe_i((int)noise_w, o, 1) & x.two_n) + (bfe_i((int)up_w, pos, 1) & x.two_q);
-                    if (kMode == 1) t += bfe_i((int)dn_w, pos, 1) & x.two_q;
-                    const int sv = (accv << 1) + hq4[j] + t + bfe_i(isw, 8 * j, 8);
                     int nv;
-                    if (kAlpha1) {
-                        nv = med3_i32(sv, lo, hi);
+                    if (kFast) {
+                        nv = med3_i32(f2 + hq4[j] + (int)bfe_u(s4, 8 * j, 8), lo, hi);
                     } else {
+                        int t = (bfe_i((int)noise_w, 4 * ai + j, 1) & x.two_n) + (bfe_i((int)up_w, pos, 1) & x.two_q);
+                        if (kMode == 1) t += bfe_i((int)dn_w, pos, 1) & x.two_q;
+                        const int sv = f2 + hq4[j] + t + bfe_i(isw, 8 * j, 8);
                         nv = sv >= x.i0 ? x.i0 - x.alpha : (sv < lo ? lo : sv);
                     }
                     isw_new = __builtin_amdgcn_perm(isw_new, (uint32_t)nv, insert_byte_sel(j));
                 }
             }
             if (kUpdate) {
-                // sign bit of byte j (bit 8 j + 7) -> bit 8 j + cpos of the plane word
-                negbits |= (isw_new >> (7 - cpos)) & (0x01010101u << cpos);
+                // sign bit of byte j (bit 8 j + 7) -> bit 8 j + a of the plane word
+                negbits |= (isw_new >> (7 - ai)) & (0x01010101u << ai);
                 if (ai < 4) is_lo[ai] = (int)isw_new; else is_hi[ai - 4] = (int)isw_new;
             }
         }
@@ -271,7 +311,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
 //   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
 //   rows    [kWaves][256] int32         row vectors of each wave's current tile
 // All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
-template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
+template <bool kFast, int kMode, int kNBF, bool kFp4>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     constexpr int kNB = 16 * kNBF;
     extern __shared__ uint32_t lds[];
@@ -388,10 +428,21 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         const int p_del = (t - a.delay + npl) % npl;
         const int q = update ? a.jperp[t] : 0;
         const int i0 = update ? a.i0[t] : 0;
+        // Counter input (Eq. 6a, with sigma = 2 x - 1 and F = 2 sum_j J_ij x_j - rowsum):
+        //   s = Is + 2 sum_j J_ij x_j + (h - rowsum) - n_rnd - q (1 + mode) + 2 n_rnd [r = +1]
+        //       + 2 q [sigma_up = +1] (+ 2 q [sigma_dn = +1] in mode 1).
+        // The fast path writes q (2 [sigma = +1] - 1) as 2 |q| [sigma = sign q] - |q|.
+        // kAccOffset is the accumulator's constant offset: the fp4 product starts from 1.5 * 2^23, so the
+        // bits of the fp32 result are kAccOffset + 2 sum_j J_ij x_j (an integer of magnitude below 2^22).
+        constexpr int kAccOffset = kFp4 ? 0x4B400000 : 0;
+        const int qa = kFast ? (q < 0 ? -q : q) : q;
         const int two_n = 2 * a.noise_amp;
-        const int two_q = 2 * q;
-        // s = Is + 2 acc + (h - rowsum) - n_rnd - q (1 + mode) + 2 n_rnd [r = +1] + 2 q [sigma_up = +1] (+ dn)
-        const int adj = -a.noise_amp - q * (kMode == 1 ? 2 : 1);
+        const int two_q = 2 * qa;
+        const int adj = -a.noise_amp - qa * (kMode == 1 ? 2 : 1);
+        // per-row constants staged with each tile: h - rowsum + row_add_h and 2 h - rowsum + row_add_e
+        const int row_add_h = adj - kAccOffset - (kFast ? 128 : 0);
+        const int row_add_e = -kAccOffset;
+        const uint32_t qflip = (kFast && q < 0) ? 0xFFFFFFFFu : 0u;
         const uint32_t* pl_cur = planes + p_cur * plane_words;
         const uint32_t* pl_del = planes + p_del * plane_words;
         uint32_t* pl_next = planes + p_next * plane_words;
@@ -405,13 +456,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             int8_t* is_lane = is_wg + (size_t)col16 * np + tile * kTileRows + 32 * g;
             const int voff = lane * 16;
             if constexpr (kFp4) {
-                // Field product on the fp4 copy of J: K steps of 128, fp32 accumulators (exact: every partial
-                // sum is an integer far below 2^24), converted to int for the epilogue.
+                // Field product on the fp4 copy of J: K steps of 128, fp32 accumulators starting at 1.5 * 2^23.
+                // Every partial sum is 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any
+                // summation order and its bits are 0x4B400000 plus that integer.
                 v4f accf[8][kNBF];
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) accf[ai][f] = v4f{0.f, 0.f, 0.f, 0.f};
+                    for (int f = 0; f < kNBF; ++f) accf[ai][f] = v4f{12582912.f, 12582912.f, 12582912.f, 12582912.f};
                 const int ns = a.prob.kp4 / 128;          // even, >= 2
                 const uint32_t* bsrc = pl_cur + col16 * cstride;
                 const int wlast = words - 1;
@@ -455,9 +507,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) acc[ai][f][j] = (int)accf[ai][f][j];
+                    for (int f = 0; f < kNBF; ++f) acc[ai][f] = __builtin_bit_cast(v4i, accf[ai][f]);
             } else {
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
@@ -528,13 +578,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             ctx.e_acc = e_acc;
             ctx.is_wg = is_wg;
             ctx.rows = rowst + wave * 256;
-            stage_rows(rowst + wave * 256, rowv, adj);
+            stage_rows(rowst + wave * 256, rowv, row_add_h, row_add_e);
             ctx.np = np;
             ctx.cstride = cstride;
             ctx.tile = tile;
             ctx.wave = wave;
             ctx.lane = lane;
-            ctx.adj = adj;
+            ctx.qflip = qflip;
             ctx.two_n = two_n;
             ctx.two_q = two_q;
             ctx.i0 = i0;
@@ -552,9 +602,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                fused_epilogue<true, kAlpha1, kMode, kNBF>(acc, cnt, ctx);
+                fused_epilogue<true, kFast, kMode, kNBF, kFp4>(acc, cnt, ctx);
             } else {
-                fused_epilogue<false, kAlpha1, kMode, kNBF>(acc, cnt, ctx);
+                fused_epilogue<false, kFast, kMode, kNBF, kFp4>(acc, cnt, ctx);
             }
         }
         __syncthreads();
@@ -603,19 +653,19 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     }
 }
 
-template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
+template <bool kFast, int kMode, int kNBF, bool kFp4>
 __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
-    sweep_block<kAlpha1, kMode, kNBF, kFp4>(a, blockIdx.x);
+    sweep_block<kFast, kMode, kNBF, kFp4>(a, blockIdx.x);
 }
 
 // Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
 // host in decreasing cost so that the largest blocks start first.
-template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
+template <bool kFast, int kMode, int kNBF, bool kFp4>
 __global__ __launch_bounds__(kThreads, 2) void sweep_batch_kernel(const SweepArgs* __restrict__ items,
                                                                    const uint32_t* __restrict__ work) {
     const uint32_t w = work[blockIdx.x];
     const SweepArgs a = items[w >> 16];
-    sweep_block<kAlpha1, kMode, kNBF, kFp4>(a, (int)(w & 0xFFFFu));
+    sweep_block<kFast, kMode, kNBF, kFp4>(a, (int)(w & 0xFFFFu));
 }
 
 // int32 J [n][n] -> P balanced int8 planes [P][np][np] (J = sum_p 256^p J_p), zero padded;
@@ -770,17 +820,17 @@ hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t
     return hipGetLastError();
 }
 
-template <bool kAlpha1, int kMode, int kNBF, bool kFp4>
+template <bool kFast, int kMode, int kNBF, bool kFp4>
 hipError_t configure_variant() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kAlpha1, kMode, kNBF, kFp4>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<kFast, kMode, kNBF, kFp4>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kAlpha1, kMode, kNBF, kFp4>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kFast, kMode, kNBF, kFp4>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     return e;
 }
 
-// Variant v: bit 3 alpha == 1, bit 2 coupling mode 1, bit 1 fp4 operands, bit 0 32 columns per workgroup.
+// Variant v: bit 3 fast epilogue, bit 2 coupling mode 1, bit 1 fp4 operands, bit 0 32 columns per workgroup.
 #define SSQA_FOR_EACH_VARIANT(X) \
     X(0, false, 0, 4, false) X(1, false, 0, 2, false) X(2, false, 0, 4, true) X(3, false, 0, 2, true) \
     X(4, false, 1, 4, false) X(5, false, 1, 2, false) X(6, false, 1, 4, true) X(7, false, 1, 2, true) \
@@ -799,8 +849,8 @@ hipError_t configure_sweep_kernels() {
     return status;
 }
 
-int sweep_variant(bool alpha1, int mode, int nb, bool fp4) {
-    return (alpha1 ? 8 : 0) + (mode ? 4 : 0) + (fp4 ? 2 : 0) + (nb == 32 ? 1 : 0);
+int sweep_variant(bool fast, int mode, int nb, bool fp4) {
+    return (fast ? 8 : 0) + (mode ? 4 : 0) + (fp4 ? 2 : 0) + (nb == 32 ? 1 : 0);
 }
 
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
@@ -825,7 +875,7 @@ hipError_t launch_sweep(const SweepArgs& a, int n_wg, hipStream_t stream) {
     if (ce != hipSuccess) return ce;
     const size_t lds = sweep_lds_bytes(a.prob.np, a.delay, a.nb);
     const dim3 grid(n_wg), block(kThreads);
-    switch (sweep_variant(a.alpha == 1, a.mode, a.nb, a.fp4 != 0)) {
+    switch (sweep_variant(a.fast != 0, a.mode, a.nb, a.fp4 != 0)) {
 #define SSQA_LAUNCH_ONE(v, al, mo, nbf, f4)                                                \
     case v:                                                                              \
         hipLaunchKernelGGL((sweep_kernel<al, mo, nbf, f4>), grid, block, lds, stream, a); \

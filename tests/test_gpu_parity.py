@@ -254,3 +254,24 @@ def test_fp4_refused_when_inexact(lib):
         run_gpu(prob, replicas=2, trials=2, cycles=3, q=[0, 0, 0], i0=[9, 9, 9], alpha=1, noise=1, delay=1, seed=0,
                 operand_format=2)
     assert ei.value.name == "SSQA_ENOTSUP"
+
+
+@pytest.mark.parametrize("n,mode,delay,j_max,fmt", [
+    (300, 1, 2, 8, 1),     # int8 operands, both neighbours, d = 2
+    (300, 1, 2, 4, 2),     # fp4 operands (every |J_ij| <= 4)
+    (200, 0, 1, 6, 0),     # one neighbour, automatic operands
+])
+def test_byte_parallel_update_with_negative_jperp(lib, n, mode, delay, j_max, fmt):
+    """alpha = 1 with small I_0, n_rnd and |J_perp| selects the byte-parallel counter update; J_perp takes
+    both signs (negative values complement the coupling bits), I_0 varies from cycle to cycle."""
+    _note(f"case byte-parallel update n={n} mode={mode} d={delay} fmt={fmt}")
+    h, J = random_ising(n, 900 + n + mode, h_max=60, j_max=j_max)
+    if fmt == 2:
+        J[np.abs(J) == 5] = 4
+    rng = np.random.default_rng(n + 17)
+    SC = 36
+    q = rng.integers(-8, 9, size=SC)      # max I_0 + 2 n_rnd + 2 |q| (1 + mode) = 40 + 20 + 32 <= 128
+    i0 = rng.integers(2, 41, size=SC)
+    kw = dict(replicas=6, trials=11, cycles=SC, q=q, i0=i0, alpha=1, noise=10, delay=delay, seed=n, mode=mode)
+    prob = lib.Problem(h, J)
+    assert_same(run_gpu(prob, operand_format=fmt, **kw), run_oracle(h, J, **kw))
