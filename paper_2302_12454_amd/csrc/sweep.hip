@@ -105,7 +105,12 @@ __device__ __forceinline__ void mma_i8(v4i (&A)[8], const v4i (&B)[kNBF], v4i (&
     }
 }
 
-// One K step on fp4 (e2m1) operands, fp32 accumulation; J is scaled by 2 (e8m0 scale 128), x by 1.
+// One fp4 (e2m1) MFMA, fp32 accumulation; J is scaled by 2 (e8m0 scale 128), x by 1.
+__device__ __forceinline__ v4f mfma_fp4(const v4i& a, const v4i& b, const v4f& c) {
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(widen(a), widen(b), c, 4, 4, 0, 128, 0, 127);
+}
+
+// One K step on fp4 operands.
 template <int kNBF, bool kReload>
 __device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (&acc)[8][kNBF],
                                         __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
@@ -113,8 +118,7 @@ __device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (
     for (int ai = 0; ai < 8; ++ai) {
 #pragma unroll
         for (int f = 0; f < kNBF; ++f)
-            acc[ai][f] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(widen(A[ai]), widen(B[f]), acc[ai][f], 4, 4,
-                                                                          0, 128, 0, 127);
+            acc[ai][f] = mfma_fp4(A[ai], B[f], acc[ai][f]);
         if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
     }
 }
@@ -138,11 +142,13 @@ __device__ __forceinline__ void prefetch_counters(v4i (&cnt)[kNBF][2], const int
 }
 
 // 4 rows of the tile's row vectors: lane l < 32 takes h - rowsum at rows 4 l .. 4 l + 3, lane l >= 32 takes
-// 2 h - rowsum at rows 4 (l - 32) .. 4 (l - 32) + 3.
+// h (fp4 operands) or 2 h - rowsum (int8 operands) at rows 4 (l - 32) .. 4 (l - 32) + 3.
+template <bool kFp4>
 __device__ __forceinline__ v4i fetch_rows(const DeviceProblem& prob, int tile) {
     int ln = threadIdx.x & 63;
     asm volatile("" : "+v"(ln));
-    return *reinterpret_cast<const v4i*>((ln < 32 ? prob.hr : prob.er) + tile * kTileRows + 4 * (ln & 31));
+    return *reinterpret_cast<const v4i*>((ln < 32 ? prob.hr : (kFp4 ? prob.h : prob.er)) + tile * kTileRows +
+                                         4 * (ln & 31));
 }
 
 // Writes the row vectors fetched by this lane into the wave's staging area, each plus its cycle constant.
@@ -227,7 +233,10 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
     const int eg = ln >> 4;
     const int word = x.tile * 4 + eg;
     const int row0 = x.tile * kTileRows + 32 * eg;
-    const int lo = -x.i0, hi = x.i0 - 1;
+    // clamp bounds of Eq. 6b, shifted by the accumulator's offset (its low byte is zero, so the low byte of a
+    // shifted counter is the counter)
+    constexpr int kOff = kFp4 ? 0x4B400000 : 0;
+    const int lo = kOff - x.i0, hi = kOff + x.i0 - 1;
     const uint32_t tn2 = (uint32_t)x.two_n * 0x00010001u;
     const uint32_t tq2 = (uint32_t)x.two_q * 0x00010001u;
 
@@ -254,8 +263,8 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
             const v4i er4 = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
-            v4i hq4;
-            if (kUpdate) hq4 = *reinterpret_cast<const v4i*>(x.rows + 32 * eg + 4 * ai);
+            v4i hq4 = v4i{0, 0, 0, 0};   // fp4: already in the accumulator
+            if (kUpdate && !kFp4) hq4 = *reinterpret_cast<const v4i*>(x.rows + 32 * eg + 4 * ai);
             uint32_t isw_new = 0;
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
             uint32_t s4 = 0;
@@ -273,14 +282,15 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
                 // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
                 ep = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep);
                 if (kUpdate) {
+                    const int base = kFp4 ? f2 : f2 + hq4[j];
                     int nv;
                     if (kFast) {
-                        nv = med3_i32(f2 + hq4[j] + (int)bfe_u(s4, 8 * j, 8), lo, hi);
+                        nv = med3_i32(base + (int)bfe_u(s4, 8 * j, 8), lo, hi);
                     } else {
                         int t = (bfe_i((int)noise_w, 4 * ai + j, 1) & x.two_n) + (bfe_i((int)up_w, pos, 1) & x.two_q);
                         if (kMode == 1) t += bfe_i((int)dn_w, pos, 1) & x.two_q;
-                        const int sv = f2 + hq4[j] + t + bfe_i(isw, 8 * j, 8);
-                        nv = sv >= x.i0 ? x.i0 - x.alpha : (sv < lo ? lo : sv);
+                        const int sv = base + t + bfe_i(isw, 8 * j, 8);
+                        nv = sv > hi ? x.i0 - x.alpha : (sv < lo ? lo : sv);
                     }
                     isw_new = __builtin_amdgcn_perm(isw_new, (uint32_t)nv, insert_byte_sel(j));
                 }
@@ -432,38 +442,45 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         //   s = Is + 2 sum_j J_ij x_j + (h - rowsum) - n_rnd - q (1 + mode) + 2 n_rnd [r = +1]
         //       + 2 q [sigma_up = +1] (+ 2 q [sigma_dn = +1] in mode 1).
         // The fast path writes q (2 [sigma = +1] - 1) as 2 |q| [sigma = sign q] - |q|.
-        // kAccOffset is the accumulator's constant offset: the fp4 product starts from 1.5 * 2^23, so the
-        // bits of the fp32 result are kAccOffset + 2 sum_j J_ij x_j (an integer of magnitude below 2^22).
+        // With fp4 operands the accumulator is an fp32 number 1.5 * 2^23 + v with v an integer below 2^22 in
+        // magnitude, whose bits are kAccOffset + v; the epilogue works on those bits directly.
         constexpr int kAccOffset = kFp4 ? 0x4B400000 : 0;
         const int qa = kFast ? (q < 0 ? -q : q) : q;
         const int two_n = 2 * a.noise_amp;
         const int two_q = 2 * qa;
         const int adj = -a.noise_amp - qa * (kMode == 1 ? 2 : 1);
-        // per-row constants staged with each tile: h - rowsum + row_add_h and 2 h - rowsum + row_add_e
-        const int row_add_h = adj - kAccOffset - (kFast ? 128 : 0);
-        const int row_add_e = -kAccOffset;
+        // The fast path adds the counters offset by 128, which the per-row constant takes back.
+        const int adj_c = adj - (kFast ? 128 : 0);
+        // Per-row constants staged with each tile (see the tile loop): the first vector (h - rowsum) gets
+        // row_add_h, the second (h for fp4, 2 h - rowsum for int8) gets row_add_e.
+        const int row_add_h = adj_c + kAccOffset;
+        const int row_add_e = kFp4 ? -adj_c - kAccOffset : 0;
         const uint32_t qflip = (kFast && q < 0) ? 0xFFFFFFFFu : 0u;
         const uint32_t* pl_cur = planes + p_cur * plane_words;
         const uint32_t* pl_del = planes + p_del * plane_words;
         uint32_t* pl_next = planes + p_next * plane_words;
 
+        // Row vectors of the wave's first tile; later tiles' are fetched during the previous tile's last K steps.
+        v4i rowv_next = fetch_rows<kFp4>(a.prob, wave);
         for (int tile = wave; tile < ntiles; tile += kWaves) {
+            // Per-row constants of this tile, staged in LDS for the first K step and the epilogue:
+            //   fp4:  [0, 128) the accumulator's start, 0x4B400000 + h - rowsum + row_add_h (as fp32 bits),
+            //         [128, 256) h - row_add_h - 0x4B400000, so that start + 2 field + this = 2 h + F;
+            //   int8: [0, 128) h - rowsum + row_add_h, [128, 256) 2 h - rowsum.
+            stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
+            const int32_t* rows_w = rowst + wave * 256;
+            const bool more = tile + kWaves < ntiles;
             v4i acc[8][kNBF];
-            // Fetched during the last K steps, for the epilogue: this lane's counters of the tile, and 4 rows
-            // of a row vector of the tile (lane l < 32: h - rowsum, lane l >= 32: 2 h - rowsum).
+            // This lane's counters of the tile, fetched during the last K steps for the epilogue.
             v4i cnt[kNBF][2];
-            v4i rowv;
             int8_t* is_lane = is_wg + (size_t)col16 * np + tile * kTileRows + 32 * g;
             const int voff = lane * 16;
             if constexpr (kFp4) {
-                // Field product on the fp4 copy of J: K steps of 128, fp32 accumulators starting at 1.5 * 2^23.
-                // Every partial sum is 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any
-                // summation order and its bits are 0x4B400000 plus that integer.
+                // Field product on the fp4 copy of J: K steps of 128 with J scaled by 2, fp32 accumulators that
+                // start from the staged per-row constant (1.5 * 2^23 plus an integer).  Every partial sum is
+                // 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any summation order and
+                // its bits are 0x4B400000 plus that integer.
                 v4f accf[8][kNBF];
-#pragma unroll
-                for (int ai = 0; ai < 8; ++ai)
-#pragma unroll
-                    for (int f = 0; f < kNBF; ++f) accf[ai][f] = v4f{12582912.f, 12582912.f, 12582912.f, 12582912.f};
                 const int ns = a.prob.kp4 / 128;          // even, >= 2
                 const uint32_t* bsrc = pl_cur + col16 * cstride;
                 const int wlast = words - 1;
@@ -483,8 +500,26 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                     for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
                 };
+                {
+                    // Step 0 starts every accumulator of row block ai from the staged constants.
+                    v4i B[kNBF];
+                    expand(B);
+                    next_b(1);
+#pragma unroll
+                    for (int ai = 0; ai < 8; ++ai) {
+                        const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * g + 4 * ai));
+#pragma unroll
+                        for (int f = 0; f < kNBF; ++f) accf[ai][f] = mfma_fp4(A0[ai], B[f], start);
+                        if (ns > 2) A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
+                    }
+                    if (ns > 2) {
+                        expand(B);
+                        next_b(2);
+                        mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
+                    }
+                }
                 // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
-                for (int s = 0; s < ns - 2; s += 2) {
+                for (int s = 2; s < ns - 2; s += 2) {
                     v4i B[kNBF];
                     expand(B);
                     next_b(s + 1);
@@ -494,12 +529,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                     mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
                 }
                 {
-                    // The last two steps: no J left to fetch; the epilogue's counters are fetched instead.
+                    // The last two steps (for ns = 2 only the second: step 0 above was the first): no J left
+                    // to fetch; the next tile's row vectors and the epilogue's counters are fetched instead.
                     v4i B[kNBF];
-                    expand(B);
-                    next_b(ns - 1);
-                    mma_fp4<kNBF, false>(A0, B, accf, j4rsrc, voff, 0);
-                    rowv = fetch_rows(a.prob, tile);
+                    if (ns > 2) {
+                        expand(B);
+                        next_b(ns - 1);
+                        mma_fp4<kNBF, false>(A0, B, accf, j4rsrc, voff, 0);
+                    }
+                    if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
                     prefetch_counters(cnt, is_lane, np);
                     expand(B);
                     mma_fp4<kNBF, false>(A1, B, accf, j4rsrc, voff, 0);
@@ -509,10 +547,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                     for (int f = 0; f < kNBF; ++f) acc[ai][f] = __builtin_bit_cast(v4i, accf[ai][f]);
             } else {
-#pragma unroll
-                for (int ai = 0; ai < 8; ++ai)
-#pragma unroll
-                    for (int f = 0; f < kNBF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
                 // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
                 // group g ends up with rows 32 g .. 32 g + 31.
                 const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
@@ -526,6 +560,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                     for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
                 };
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai)
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
                 for (int p = P - 1; p >= 0; --p) {
                     if (p < P - 1) {
 #pragma unroll
@@ -554,12 +592,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                         mma_i8<kNBF, true>(A1, B, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
                     }
                     {
+                        // the last two steps: no J left to fetch
                         v4i B[kNBF];
                         expand(B);
                         next_b(nsteps - 1);
                         mma_i8<kNBF, false>(A0, B, acc, jrsrc, voff, 0);
                         if (p == 0) {
-                            rowv = fetch_rows(a.prob, tile);
+                            if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
                             prefetch_counters(cnt, is_lane, np);
                         }
                         expand(B);
@@ -577,8 +616,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             ctx.colinfo = colinfo;
             ctx.e_acc = e_acc;
             ctx.is_wg = is_wg;
-            ctx.rows = rowst + wave * 256;
-            stage_rows(rowst + wave * 256, rowv, row_add_h, row_add_e);
+            ctx.rows = rows_w;
             ctx.np = np;
             ctx.cstride = cstride;
             ctx.tile = tile;
