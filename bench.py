@@ -31,7 +31,8 @@ FP4_MFMA_PEAK = 10.1e15      # MI355X dense fp4 MFMA, flop/s
 HBM_PEAK = 8.0e12            # bytes/s
 
 METRIC = "spin-updates/s and time-to-solution @99% success (N=2500 GI), batched vs plain"
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_12454_amd", "csrc", "sweep.hip")
+# the sources the sweep kernel is compiled from; the committed counters are valid for this exact text
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_12454_amd", "csrc", f) for f in ("sweep.hip", "internal.hpp", "philox.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_gi50_traffic.json")
 
 
@@ -43,8 +44,11 @@ def measured_traffic(dtype):
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(KERNEL_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in KERNEL_SOURCES:
+            with open(path, "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != digest or rec.get("operands", "int8") != dtype:
@@ -165,14 +169,17 @@ def batched_vs_plain(args):
             return None
         return t * math.log(0.01) / math.log(1.0 - p)
 
+    blocks = batch.blocks
+    fp4 = all(p.fp4_exact for p, _ in jobs)
     batch.close()
     return {
         "workload": f"batch{len(jobs)}: GI n ~ U{{10..50}}, p ~ U[0.3, 0.7], R={R}, T={T}, SC={SC}, tau={base.tau}",
-        "instances": len(jobs), "blocks": None, "spin_updates": updates,
+        "instances": len(jobs), "workgroups": blocks, "spin_updates": updates,
         "batched_ms": batched_ms, "plain_ms": plain_ms, "speedup": plain_ms / batched_ms,
         "batched_spin_updates_per_s": updates / (batched_ms / 1e3),
         "plain_spin_updates_per_s": updates / (plain_ms / 1e3),
-        "batched_int8_frac": ops / (batched_ms / 1e3) / INT8_MFMA_PEAK,
+        "operands": "fp4" if fp4 else "int8",
+        "batched_mfma_frac": ops / (batched_ms / 1e3) / (FP4_MFMA_PEAK if fp4 else INT8_MFMA_PEAK),
         "p_s_mean": float(np.mean(p_batched)), "p_s_min": ps_min,
         "tts99_all_instances_batched_s": tts(batched_ms / 1e3, ps_min),
         "tts99_all_instances_plain_s": tts(plain_ms / 1e3, ps_min),

@@ -21,14 +21,6 @@ constexpr uint32_t kPhiloxMul1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxWeyl0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxWeyl1 = 0xBB67AE85u;
 
-__host__ __device__ inline uint32_t mul_hi32(uint32_t a, uint32_t b) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __umulhi(a, b);
-#else
-    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
-#endif
-}
-
 __host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                   uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -37,8 +29,11 @@ __host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
             k0 += kPhiloxWeyl0;
             k1 += kPhiloxWeyl1;
         }
-        const uint32_t hi0 = mul_hi32(kPhiloxMul0, c0), lo0 = kPhiloxMul0 * c0;
-        const uint32_t hi1 = mul_hi32(kPhiloxMul1, c2), lo1 = kPhiloxMul1 * c2;
+        // one 32 x 32 -> 64-bit product per multiplier (a single v_mad_u64_u32 on the GPU)
+        const uint64_t p0 = (uint64_t)kPhiloxMul0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxMul1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
