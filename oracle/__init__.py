@@ -19,10 +19,12 @@ below 2**53):
               Hamiltonian (Eq. 1 / Eq. 5) and the QMC Hamiltonian (Eq. 4).
 * ``metrics`` success probability over trials and time-to-solution (Eq. 10),
               equivalent cycles (Eq. 9).
+* ``sa``      the traditional simulated-annealing baseline of Section 4.4 and
+              Table 4 (serial single-spin Metropolis).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test to
 something other than itself (published test vectors, brute force, closed forms,
 special cases, values printed in the paper); see the test files.
 """
 
-from . import gi, metrics, philox, ssqa  # noqa: F401
+from . import gi, metrics, philox, sa, ssqa  # noqa: F401
