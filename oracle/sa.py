@@ -51,10 +51,11 @@ _TAYLOR = [float(Fraction(1, math.factorial(k))) for k in range(14)]
 
 
 def exp_neg(x: float) -> float:
-    """exp(-x) for x >= 0 by a fixed operation sequence (see module doc); 0 beyond x = 745.
-    Relative error below 1e-12 over [0, 745]."""
+    """exp(-x) for x >= 0 by a fixed operation sequence (see module doc); 0 beyond x = 700, so
+    that every value stays a normal double and the final scaling by 2^-n is exact.  Relative error
+    below 1e-12 over [0, 700]."""
     x = float(x)
-    if x > 745.0:
+    if x > 700.0:
         return 0.0
     n = math.floor(x * _INV_LN2 + 0.5)          # nearest integer to x / ln 2
     r = n * _LN2 - x                            # -(x - n ln 2), |r| <= ln 2 / 2 up to rounding
