@@ -275,6 +275,54 @@ ssqa_status ssqa_qmc_energy(ssqa_problem_t problem, const int8_t* counters, int3
                             int32_t jperp, int64_t* energies, void* hip_stream);
 
 /* ------------------------------------------------------------------------------------------- */
+/* Traditional simulated annealing: the SA baseline of Section 4.4 and Table 4.                  */
+/* ------------------------------------------------------------------------------------------- */
+
+/*
+ * Serial single-spin Metropolis annealing of `trials` independent chains of the problem (one wave
+ * of 64 lanes per chain).  Cycle t picks one spin i uniformly at random, computes the energy change
+ * of flipping it, dE = 2 sigma_i (h_i + sum_j J_ij sigma_j) (H of Eq. 1), and accepts the flip if
+ * dE <= 0, else with probability exp(-dE beta(t)).  beta is the inverse temperature at the integer
+ * scale of the problem (ssqa_sa_schedule builds Section 4.4's schedule).
+ * Random stream (Philox4x32-10, key = seed halves): the initial spins use counter
+ * (i >> 7, 0xFFFFFFFE, 0, b), spin i taking bit (i & 31) of word (i & 127) >> 5 (bit 1 = +1); cycle
+ * t uses counter (t, 0xFFFFFFFF, 0, b): i = (w0 * N) >> 32, and the flip is accepted iff
+ * w1 < ssqa_sa_accept_threshold(dE, beta(t)).
+ */
+typedef struct ssqa_sa_params {
+    int32_t trials;            /* T >= 1, at most 2^24                                             */
+    int32_t cycles;            /* attempted flips per chain, >= 0                                  */
+    const double* beta;        /* host double [cycles]: finite, >= 0                               */
+    uint64_t seed;
+    int64_t target_energy;     /* E* (for first_hit), or SSQA_NO_TARGET                            */
+} ssqa_sa_params;
+
+typedef struct ssqa_sa_outputs {
+    int64_t* best_energy;      /* device int64 [T]: minimum energy over t in [0, cycles]           */
+    int32_t* first_hit;        /* device int32 [T]: first t in [0, cycles] whose state (after t
+                                  cycles) has energy E*, else -1                                   */
+    int64_t* final_energy;     /* device int64 [T], or NULL                                        */
+    int8_t* final_spins;       /* device int8 [T][N] (+-1), or NULL                                */
+    int64_t* energy_trace;     /* device int64 [cycles + 1][T]: energy after t cycles, or NULL     */
+} ssqa_sa_outputs;
+
+/* Asynchronous on hip_stream.  SSQA_EINVAL for bad sizes, NULL required pointers or a beta that is
+ * negative or not finite; SSQA_ENOTSUP when N exceeds 32768 (the chain's fields live in LDS). */
+ssqa_status ssqa_sa_anneal(ssqa_problem_t problem, const ssqa_sa_params* params, const ssqa_sa_outputs* outputs,
+                           void* hip_stream);
+
+/* beta(t) = 1/(scale t_start) + t Delta, Delta = (1/(scale t_end) - 1/(scale t_start)) / (cycles - 1):
+ * 1/T grows by the same amount every cycle (Section 4.4), from t_start at t = 0 to t_end at the last
+ * cycle, at the integer scale `scale` (energies there are scale times the paper's).  Host output
+ * double [cycles].  SSQA_EINVAL unless cycles >= 1, scale >= 1 and 0 < t_end, t_start. */
+ssqa_status ssqa_sa_schedule(int32_t cycles, double t_start, double t_end, int32_t scale, double* beta);
+
+/* 2^32 exp(-de beta) (de >= 0, beta >= 0), evaluated by the fixed sequence of correctly rounded double
+ * operations the GPU chain uses: n = floor(x / ln 2 + 1/2) with x = de beta, r = n ln 2 - x, the degree-13
+ * Taylor polynomial of exp(r) in Horner form, scaled by 2^(32 - n); 0 when x > 700. */
+double ssqa_sa_accept_threshold(int64_t de, double beta);
+
+/* ------------------------------------------------------------------------------------------- */
 /* Host helpers: schedules and the graph-isomorphism mapping (no device work).                 */
 /* ------------------------------------------------------------------------------------------- */
 

@@ -11,6 +11,7 @@ from .api import (  # noqa: F401
     AnnealResult,
     Batch,
     Problem,
+    SAResult,
     Server,
     SSQAError,
     ssqa_anneal,
@@ -21,6 +22,9 @@ from .api import (  # noqa: F401
     ssqa_jperp_schedule,
     ssqa_philox4x32_10,
     ssqa_qmc_energy,
+    ssqa_sa_accept_threshold,
+    ssqa_sa_anneal,
+    ssqa_sa_schedule,
     ssqa_server_create,
     ssqa_ssa_i0_schedule,
 )

@@ -42,6 +42,26 @@ class AnnealOutputs(ctypes.Structure):
     ]
 
 
+class SAParams(ctypes.Structure):
+    _fields_ = [
+        ("trials", ctypes.c_int32),
+        ("cycles", ctypes.c_int32),
+        ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("seed", ctypes.c_uint64),
+        ("target_energy", ctypes.c_int64),
+    ]
+
+
+class SAOutputs(ctypes.Structure):
+    _fields_ = [
+        ("best_energy", ctypes.c_void_p),
+        ("first_hit", ctypes.c_void_p),
+        ("final_energy", ctypes.c_void_p),
+        ("final_spins", ctypes.c_void_p),
+        ("energy_trace", ctypes.c_void_p),
+    ]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [
         ("device", ctypes.c_int32),
@@ -106,6 +126,11 @@ SIGNATURES = {
     "ssqa_gi_to_ising": (ctypes.c_int, [ctypes.c_int32, c_uint8_p, c_uint8_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, c_int32_p, c_int32_p, c_int64_p]),
     "ssqa_philox4x32_10": (None, [c_uint32_p, c_uint32_p, c_uint32_p]),
+    "ssqa_sa_anneal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SAParams), ctypes.POINTER(SAOutputs),
+                                      ctypes.c_void_p]),
+    "ssqa_sa_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "ssqa_sa_accept_threshold": (ctypes.c_double, [ctypes.c_int64, ctypes.c_double]),
     "ssqa_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(AnnealParams),
                                          ctypes.POINTER(AnnealOutputs), ctypes.POINTER(ctypes.c_void_p)]),
     "ssqa_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),

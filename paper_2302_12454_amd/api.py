@@ -246,6 +246,60 @@ def ssqa_qmc_energy(problem: Problem, counters, jperp: int, stream=None):
     return energies
 
 
+@dataclass
+class SAResult:
+    best_energy: object            # torch int64 [T]
+    first_hit: object              # torch int32 [T]
+    final_energy: object = None    # torch int64 [T]
+    final_spins: object = None     # torch int8 [T, N]
+    energy_trace: object = None    # torch int64 [cycles + 1, T]
+
+
+def ssqa_sa_anneal(problem: Problem, *, trials: int, beta, seed: int = 0, target=None, final_state: bool = True,
+                   trace: bool = False, stream=None) -> SAResult:
+    """Serial single-spin Metropolis chains (the SA baseline of Section 4.4) on the problem's device;
+    ``beta`` is the per-cycle inverse temperature at the problem's integer scale."""
+    import torch
+    lib = _lib.load()
+    beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+    cycles = int(beta.shape[0])
+    dev = torch.device("cuda", problem.device)
+    res = SAResult(best_energy=torch.empty(trials, dtype=torch.int64, device=dev),
+                   first_hit=torch.empty(trials, dtype=torch.int32, device=dev))
+    if final_state:
+        res.final_energy = torch.empty(trials, dtype=torch.int64, device=dev)
+        res.final_spins = torch.empty((trials, problem.n), dtype=torch.int8, device=dev)
+    if trace:
+        res.energy_trace = torch.empty((cycles + 1, trials), dtype=torch.int64, device=dev)
+    p = _lib.SAParams()
+    p.trials = int(trials)
+    p.cycles = cycles
+    p.beta = _ptr(beta, ctypes.c_double)
+    p.seed = int(seed) & (2 ** 64 - 1)
+    p.target_energy = SSQA_NO_TARGET if target is None else int(target)
+    o = _lib.SAOutputs()
+
+    def ptr(t):
+        return None if t is None else t.data_ptr()
+
+    o.best_energy, o.first_hit = ptr(res.best_energy), ptr(res.first_hit)
+    o.final_energy, o.final_spins, o.energy_trace = ptr(res.final_energy), ptr(res.final_spins), ptr(res.energy_trace)
+    _check(lib.ssqa_sa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
+           "ssqa_sa_anneal")
+    return res
+
+
+def ssqa_sa_schedule(cycles: int, t_start: float = 1000.0, t_end: float = 0.1, scale: int = 12) -> np.ndarray:
+    out = np.zeros(max(cycles, 1), dtype=np.float64)
+    _check(_lib.load().ssqa_sa_schedule(cycles, float(t_start), float(t_end), scale, _ptr(out, ctypes.c_double)),
+           "ssqa_sa_schedule")
+    return out[:cycles]
+
+
+def ssqa_sa_accept_threshold(de: int, beta: float) -> float:
+    return float(_lib.load().ssqa_sa_accept_threshold(int(de), float(beta)))
+
+
 def ssqa_jperp_schedule(cycles: int, tau: int, beta: int, jmin_num: int, jmax_num: int, den: int,
                         scale: int) -> np.ndarray:
     out = np.zeros(max(cycles, 1), dtype=np.int32)

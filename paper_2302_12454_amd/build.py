@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libssqa.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["sweep.hip", "api.cpp", "host.cpp", "server.cpp"]
+SOURCES = ["sweep.hip", "sa.hip", "api.cpp", "host.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 

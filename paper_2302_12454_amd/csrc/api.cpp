@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -502,6 +503,47 @@ ssqa_status ssqa_qmc_energy(ssqa_problem_t prob, const int8_t* counters, int32_t
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
     SSQA_HIP(launch_qmc_energy(prob->dev, counters, trials, replicas, jperp, energies,
                                reinterpret_cast<hipStream_t>(hip_stream)), "qmc_energy");
+    return SSQA_OK;
+}
+
+ssqa_status ssqa_sa_anneal(ssqa_problem_t prob, const ssqa_sa_params* pa, const ssqa_sa_outputs* out,
+                           void* hip_stream) {
+    g_last_error.clear();
+    if (!prob || !pa || !out) return fail(SSQA_EINVAL, "NULL problem, params or outputs");
+    if (pa->trials < 1 || pa->trials > (1 << 24)) return fail(SSQA_EINVAL, "trials = %d outside [1, 2^24]", pa->trials);
+    if (pa->cycles < 0) return fail(SSQA_EINVAL, "cycles < 0");
+    if (pa->cycles > 0 && !pa->beta) return fail(SSQA_EINVAL, "beta is required");
+    for (int t = 0; t < pa->cycles; ++t)
+        if (!(pa->beta[t] >= 0.0) || !std::isfinite(pa->beta[t]))
+            return fail(SSQA_EINVAL, "beta[%d] is negative or not finite", t);
+    if (!out->best_energy || !out->first_hit) return fail(SSQA_EINVAL, "best_energy and first_hit are required");
+    if (sa_waves_per_group(prob->dev.np) < 1) return fail(SSQA_ENOTSUP, "N = %d: one chain does not fit in LDS", prob->dev.n);
+    DeviceGuard guard(prob->device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice(%d) failed", prob->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    retain_pool_memory(prob->device);
+    double* d_beta = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&d_beta), sizeof(double) * std::max(pa->cycles, 1), stream);
+    if (e == hipSuccess && pa->cycles > 0)
+        e = hipMemcpyAsync(d_beta, pa->beta, sizeof(double) * pa->cycles, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+        SAArgs a{};
+        a.prob = prob->dev;
+        a.T = pa->trials;
+        a.cycles = pa->cycles;
+        a.beta = d_beta;
+        a.key0 = (uint32_t)(pa->seed & 0xFFFFFFFFu);
+        a.key1 = (uint32_t)(pa->seed >> 32);
+        a.target = pa->target_energy;
+        a.best = out->best_energy;
+        a.first_hit = out->first_hit;
+        a.final_energy = out->final_energy;
+        a.final_spins = out->final_spins;
+        a.trace = out->energy_trace;
+        e = launch_sa(a, stream);
+    }
+    if (d_beta) (void)hipFreeAsync(d_beta, stream);
+    if (e != hipSuccess) return hip_fail(e, "sa_anneal");
     return SSQA_OK;
 }
 

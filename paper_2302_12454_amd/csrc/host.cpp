@@ -27,6 +27,22 @@ ssqa_status ssqa_jperp_schedule(int32_t cycles, int32_t tau, int32_t beta, int32
     return SSQA_OK;
 }
 
+// Section 4.4 (SA): 1/T(t+1) = 1/T(t) + Delta every cycle, from t_start at t = 0 to t_end at the last
+// cycle; beta(t) = 1/(scale T(t)) = b0 + t Delta, each value from one product and one sum.
+ssqa_status ssqa_sa_schedule(int32_t cycles, double t_start, double t_end, int32_t scale, double* beta) {
+#pragma clang fp contract(off)
+    if (cycles < 1 || scale < 1 || !beta || !(t_start > 0.0) || !(t_end > 0.0)) return SSQA_EINVAL;
+    const double b0 = 1.0 / ((double)scale * t_start);
+    const double b1 = 1.0 / ((double)scale * t_end);
+    if (cycles == 1) {
+        beta[0] = b0;
+        return SSQA_OK;
+    }
+    const double delta = (b1 - b0) / (double)(cycles - 1);
+    for (int t = 0; t < cycles; ++t) beta[t] = b0 + (double)t * delta;
+    return SSQA_OK;
+}
+
 // Section 4.4: I_0 from i0_min multiplied by growth every tau cycles until i0_max, tau cycles at
 // i0_max, then again from i0_min.
 ssqa_status ssqa_ssa_i0_schedule(int32_t cycles, int32_t tau, int32_t growth, int32_t i0_min, int32_t i0_max,

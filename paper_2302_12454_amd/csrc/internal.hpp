@@ -110,6 +110,31 @@ hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t
 hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, int32_t trials, int32_t R,
                              int32_t jperp, int64_t* out, hipStream_t stream);
 
+
+// Arguments of the simulated-annealing baseline kernel (sa.hip): one wave per chain.
+struct SAArgs {
+    DeviceProblem prob;
+    int32_t T;              // chains (trials)
+    int32_t cycles;         // attempted flips per chain
+    const double* beta;     // device [cycles]: inverse temperature at the integer scale
+    uint32_t key0, key1;
+    int64_t target;         // INT64_MIN for none
+    int64_t* best;          // [T]
+    int32_t* first_hit;     // [T]
+    int64_t* final_energy;  // [T] or nullptr
+    int8_t* final_spins;    // [T][n] or nullptr
+    int64_t* trace;         // [(cycles + 1)][T] or nullptr
+};
+
+// LDS words per chain: np int32 fields and np int8 spins.
+__host__ __device__ inline int sa_lds_words(int np) { return np + np / 4; }
+// Chains per workgroup that fit 160 KiB of LDS (at most 4); 0 when one does not.
+int sa_waves_per_group(int np);
+hipError_t launch_sa(const SAArgs& args, hipStream_t stream);
+// 2^32 exp(-de beta) by a fixed sequence of rounded double operations (host and device alike).
+__host__ __device__ double sa_exp_neg(double x);
+__host__ __device__ double sa_accept_threshold(long long de, double beta);
+
 }  // namespace ssqa
 
 // ---------------------------------------------------------------------------------------------

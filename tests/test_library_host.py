@@ -13,7 +13,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import gi, philox, ssqa
+from oracle import gi, philox, sa, ssqa
 from synth import random_gi_pair
 
 lib_mod = pytest.importorskip("paper_2302_12454_amd._lib")
@@ -121,3 +121,31 @@ def test_no_device_is_reported_not_faked(lib):
         pytest.skip("a GPU is present")
     st, _ = _create(lib, 3, np.zeros(3), np.zeros((3, 3)))
     assert st == -4
+
+
+@pytest.mark.parametrize("cycles,t0,t1,scale", [(40000, 1000.0, 0.1, 12), (1, 5.0, 1.0, 4), (7, 3.5, 0.25, 1),
+                                                (1600, 1000.0, 0.1, 12)])
+def test_sa_schedule_matches_oracle(cycles, t0, t1, scale):
+    import paper_2302_12454_amd as L
+    assert np.array_equal(L.ssqa_sa_schedule(cycles, t0, t1, scale), sa.sa_schedule(cycles, t0, t1, scale))
+
+
+def test_sa_schedule_rejects_bad_arguments(lib):
+    out = (ctypes.c_double * 4)()
+    assert lib.ssqa_sa_schedule(0, 1.0, 0.1, 12, out) == -1
+    assert lib.ssqa_sa_schedule(4, 0.0, 0.1, 12, out) == -1
+    assert lib.ssqa_sa_schedule(4, 1.0, 0.1, 0, out) == -1
+
+
+def test_sa_accept_threshold_matches_oracle_bit_for_bit(lib):
+    """The library's acceptance threshold (the function its GPU chains evaluate) equals the oracle's for
+    every tested (dE, beta), so both take every acceptance decision identically."""
+    rng = np.random.default_rng(3)
+    betas = np.concatenate([sa.sa_schedule(40000, 1000.0, 0.1, 12)[::97], rng.uniform(0, 2, 300), [0.0, 1e-300, 5.0]])
+    des = np.concatenate([np.arange(0, 200), rng.integers(1, 20000, 300), [699, 700, 701, 100000]])
+    for beta in betas:
+        for de in des[:: max(1, len(des) // 60)]:
+            assert lib.ssqa_sa_accept_threshold(int(de), float(beta)) == sa.accept_threshold(int(de), float(beta)), (de, beta)
+    for x in np.linspace(0.0, 700.0, 5001):
+        assert lib.ssqa_sa_accept_threshold(1, float(x)) == sa.accept_threshold(1, float(x)), x
+    assert lib.ssqa_sa_accept_threshold(1, 700.0000001) == 0.0
