@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512", "serve", "sweeps"])
+    ap.add_argument("--workload", default="gi50", choices=["gi5", "gi20", "gi50", "batch512", "serve", "sweeps", "table4"])
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serve workload")
     ap.add_argument("--serve-load", type=float, nargs="*", default=[0.5, 0.8],
                     help="offered loads of the serve workload, as fractions of the measured saturation rate")
@@ -261,6 +261,79 @@ def serve_workload(args):
             "saturation": dict(sat, qps=rate), "loads": loads}
 
 
+def table4_workload(args):
+    """Table 4's comparison on synthetic GI instances G(n, 0.5) (graph seed n) for N = n^2 = 25 .. 2500,
+    100 trials per method, each method's trials in one launch on the GPU:
+    * SA (Section 4.4): serial single-spin Metropolis, 40,000 cycles, T from 1000 to 0.1 (1/T linear);
+    * SSA (Section 4.4): R = 1, no coupling, 40,000 cycles, I_0 doubling from 1 to 16 every tau = 10
+      cycles, n_rnd = 1, at integer scale 4;
+    * SSQA: R = 25, SC = 1600 (EC = 40,000), tau = 100, Table 2 parameters, at integer scale 12.
+    P_s counts trials whose best energy reached E*; t is the launch's HIP-event time for all 100
+    trials; TTS99 = t ln(0.01) / ln(1 - P_s) (Eq. 10)."""
+    import numpy as np
+    import torch
+    import paper_2302_12454_amd as lib
+    from synth import WORKLOADS, random_gi_pair
+
+    base = WORKLOADS["gi50"]
+    T = 100
+    stream = torch.cuda.current_stream()
+    rows = []
+
+    def timed(fn):
+        fn()                                   # warm (first launch of each kernel variant)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / 1e3
+
+    def tts(t, p):
+        if p >= 1.0:
+            return t
+        if p <= 0.0:
+            return None
+        return t * math.log(0.01) / math.log(1.0 - p)
+
+    for n in (5, 10, 20, 25, 35, 45, 50):
+        pair = random_gi_pair(n, 0.5, n)
+        h12, J12, e12 = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, 12)
+        h4, J4, e4 = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, 4)
+        p12, p4 = lib.Problem(h12, J12, device=0), lib.Problem(h4, J4, device=0)
+        row = {"N": n * n, "e_star_scale12": int(e12)}
+        # SSQA, Table 4 configuration
+        SC = 1600
+        q = lib.ssqa_jperp_schedule(SC, 100, base.beta, 0, 1, 2, 12)
+        i0 = np.full(SC, 24, dtype=np.int32)
+        res, t = timed(lambda: lib.ssqa_anneal(p12, replicas=25, trials=T, cycles=SC, jperp=q, i0=i0, alpha=1,
+                                               noise_amp=12, delay=1, seed=n, target=e12, stream=stream))
+        ps = float((res.best_energy.cpu().numpy() == e12).mean())
+        row["ssqa"] = {"p_s": ps, "t_s": t, "tts99_s": tts(t, ps)}
+        # SSA, Section 4.4 at scale 4
+        C = 40000
+        i0s = lib.ssqa_ssa_i0_schedule(C, 10, 2, 1, 16, 4)
+        zeros = np.zeros(C, dtype=np.int32)
+        res, t = timed(lambda: lib.ssqa_anneal(p4, replicas=1, trials=T, cycles=C, jperp=zeros, i0=i0s, alpha=1,
+                                               noise_amp=4, delay=1, seed=n, target=e4, stream=stream))
+        ps = float((res.best_energy.cpu().numpy() == e4).mean())
+        row["ssa"] = {"p_s": ps, "t_s": t, "tts99_s": tts(t, ps)}
+        # SA, Section 4.4
+        beta = lib.ssqa_sa_schedule(C, 1000.0, 0.1, 12)
+        res, t = timed(lambda: lib.ssqa_sa_anneal(p12, trials=T, beta=beta, seed=n, target=e12, final_state=False,
+                                                  stream=stream))
+        ps = float((res.best_energy.cpu().numpy() == e12).mean())
+        row["sa"] = {"p_s": ps, "t_s": t, "tts99_s": tts(t, ps)}
+        rows.append(row)
+        print(f"N={n * n}: SA {row['sa']['p_s']:.2f} SSA {row['ssa']['p_s']:.2f} SSQA {row['ssqa']['p_s']:.2f}",
+              file=sys.stderr, flush=True)
+        p12.close()
+        p4.close()
+    return {"workload": "table4: GI G(n, 0.5), graph seed n, n = 5 .. 50; 100 trials per method", "rows": rows,
+            "paper_hardware": "MATLAB R2020b, AMD Ryzen 9 5950X (Table 4 t is per trial on that CPU)"}
+
+
 def sweeps_workload(args):
     """The paper's experimental design on synthetic GI instances (n = 30, 40, 50; graph seeds 30, 40, 50),
     100 trials each, the SSQA schedule of Table 2:
@@ -366,6 +439,9 @@ def main():
         return
     if args.workload == "sweeps":
         print(json.dumps({"metric": METRIC, "sweeps": sweeps_workload(args)}), flush=True)
+        return
+    if args.workload == "table4":
+        print(json.dumps({"metric": METRIC, "table4": table4_workload(args)}), flush=True)
         return
     wl = WORKLOADS[args.workload]
     pair = random_gi_pair(wl.n, wl.p, wl.graph_seed)
