@@ -52,12 +52,15 @@ struct Request {
     double submit_s = 0, admit_s = -1, done_s = -1;
 };
 
+// Device bytes of one admitted request: int8 planes, the fp4 copy of J (counted whether or not the
+// problem turns out to be fp4-exact), row vectors, counters, bit-plane history, outputs, schedules.
 int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa, int nb) {
     const int64_t np = (n + kTileRows - 1) / kTileRows * kTileRows;
+    const int64_t kp4 = (np + 255) / 256 * 256;
     const int64_t tpw = nb / pa.replicas;
     const int64_t n_wg = (pa.trials + tpw - 1) / tpw;
-    return planes_hint * np * np + 12 * np + n_wg * nb * np + n_wg * std::max(pa.delay, 1) * nb * np / 8 +
-           12LL * pa.trials + 8LL * std::max(pa.cycles, 1) + 1024;
+    return planes_hint * np * np + np * kp4 / 2 + 12 * np + n_wg * nb * np +
+           n_wg * std::max(pa.delay, 1) * nb * np / 8 + 12LL * pa.trials + 8LL * std::max(pa.cycles, 1) + 1024;
 }
 
 }  // namespace
