@@ -95,6 +95,32 @@ int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
     return 32;
 }
 
+int device_cu_count(int device) {
+    static int counts[64] = {};
+    if (device < 0 || device >= 64) return 256;
+    if (counts[device] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v < 1) v = 256;
+        counts[device] = v;
+    }
+    return counts[device];
+}
+
+// Layout of a plain anneal.  Packing whole workgroups (as many trials as fit) gives the best J reuse
+// once there are enough workgroups for every CU twice over; a smaller anneal is spread instead (the
+// narrow block when the replicas fit it, and fewer trials per workgroup, leaving columns unused), so
+// that its latency is not set by a handful of CUs.  Results do not depend on the layout.
+PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    const int R = pa->replicas, T = pa->trials;
+    const int target = 2 * device_cu_count(prob->device);
+    int nb = block_columns(prob, pa);
+    if (pa->block_columns == 0 && nb == 64 && R <= 32 && (T + 64 / R - 1) / (64 / R) < target) nb = 32;
+    const int full = nb / R;
+    int tpw = full;
+    if ((T + full - 1) / full < target) tpw = std::max(1, (T + target - 1) / target);
+    return PlainLayout{nb, tpw, (T + tpw - 1) / tpw};
+}
+
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out) {
     const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
     if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
@@ -126,10 +152,10 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
 }
 
 SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
-                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist) {
+                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist, int nb, int tpw) {
     SweepArgs a{};
-    const int nb = block_columns(prob, pa);
-    const int tpw = nb / pa->replicas;
+    if (nb == 0) nb = block_columns(prob, pa);
+    if (tpw == 0) tpw = nb / pa->replicas;
     a.prob = prob->dev;
     a.nb = nb;
     a.fp4 = use_fp4(prob, pa) ? 1 : 0;
@@ -283,9 +309,8 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     retain_pool_memory(prob->device);
-    const int nb = block_columns(prob, pa);
-    const int tpw = nb / R;
-    const int n_wg = (T + tpw - 1) / tpw;
+    const PlainLayout lay = plain_layout(prob, pa);
+    const int nb = lay.nb, tpw = lay.tpw, n_wg = lay.n_wg;
     const int np = prob->dev.np;
     const size_t is_bytes = (size_t)n_wg * nb * np;
     const size_t hist_bytes = (size_t)n_wg * std::max(pa->delay, 1) * nb * (np / 32) * 4;
@@ -304,7 +329,7 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host schedules may be freed on return
 
     if (e == hipSuccess) {
-        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist);
+        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist, nb, tpw);
         const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(SC, 1);
         int t = 0;
         do {

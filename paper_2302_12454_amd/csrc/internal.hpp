@@ -174,9 +174,17 @@ bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Full argument check of one anneal; records the reason on failure.
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out);
-// Kernel arguments of one anneal (t_begin / t_end / final_pass left for the caller).
+// Kernel arguments of one anneal (t_begin / t_end / final_pass left for the caller).  nb and tpw
+// (columns and trials per workgroup) default to the packed layout of block_columns when 0.
 SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
-                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist);
+                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist, int nb = 0,
+                    int tpw = 0);
+// Workgroup layout of a plain anneal (ssqa_anneal): columns and trials per workgroup, workgroups.
+struct PlainLayout {
+    int nb, tpw, n_wg;
+};
+PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+int device_cu_count(int device);
 // Keep freed stream-ordered allocations in the device pool.
 void retain_pool_memory(int device);
 
