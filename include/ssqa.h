@@ -92,6 +92,21 @@ int32_t ssqa_problem_fp4_exact(ssqa_problem_t problem);
 
 #define SSQA_NO_TARGET INT64_MIN
 
+/*
+ * State of an anneal after t cycles, in a layout that does not depend on how the library tiles the
+ * work (caller-owned DEVICE buffers on the problem's device):
+ *   counters : int8 [T * R * N], Is(t) of spin i of replica k of trial b at (b * R + k) * N + i;
+ *   history  : uint32 [T * R * d * W] with W = ceil(N / 32), sigma(t - s) for s = 1 .. d at
+ *              ((b * R + k) * d + (s - 1)) * W + (i >> 5), bit i & 31, bit 1 meaning +1; unused
+ *              (may be NULL) when d = 0.
+ * sigma(t) itself is the sign of the counters (Eq. 6c).  The random stream is keyed by the absolute
+ * cycle, so an anneal resumed from a checkpoint at cycle t continues bit for bit as if uninterrupted.
+ */
+typedef struct ssqa_anneal_state {
+    int8_t* counters;
+    uint32_t* history;
+} ssqa_anneal_state;
+
 typedef struct ssqa_anneal_params {
     int32_t replicas;          /* R >= 1 (Eq. 4); replica k couples to replica (k+1) mod R      */
     int32_t trials;            /* T >= 1 independent trials                                     */
@@ -115,6 +130,12 @@ typedef struct ssqa_anneal_params {
                                   else int8 planes); 1 = int8 planes; 2 = fp4 (e2m1, fp32
                                   accumulation, exact under the same conditions; SSQA_ENOTSUP
                                   otherwise).  Results do not depend on it                         */
+    int32_t start_cycle;       /* 0 for a fresh anneal; t0 in (0, cycles]: continue from the state
+                                  `resume` holds after t0 cycles (best_energy and first_hit are then
+                                  read as well as written: they must hold that run's values)      */
+    int32_t stop_cycle;        /* 0 or cycles: run to the end (including the energy of sigma(SC));
+                                  t1 in (start_cycle, cycles): stop after cycle t1 - 1            */
+    const ssqa_anneal_state* resume;   /* required when start_cycle > 0, else ignored            */
 } ssqa_anneal_params;
 
 typedef struct ssqa_anneal_outputs {
@@ -124,6 +145,8 @@ typedef struct ssqa_anneal_outputs {
     int32_t* energy_trace;     /* device int32 [(SC + 1) * T * R] or NULL: H_p of replica k of
                                   trial b at cycle t at index (t * T + b) * R + k                */
     int8_t* final_is;          /* device int8 [T * R * N] or NULL: Is(SC) at (b * R + k) * N + i */
+    const ssqa_anneal_state* checkpoint;   /* or NULL: receives the state after the last cycle run
+                                  (cycle stop_cycle, or SC)                                        */
 } ssqa_anneal_outputs;
 
 /*

@@ -9,6 +9,7 @@ loudly if it has not been built.
 from .api import (  # noqa: F401
     SSQA_NO_TARGET,
     AnnealResult,
+    AnnealState,
     Batch,
     Problem,
     SAResult,

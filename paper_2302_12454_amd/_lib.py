@@ -14,6 +14,13 @@ c_uint32_p = ctypes.POINTER(ctypes.c_uint32)
 c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
 
 
+class AnnealState(ctypes.Structure):
+    _fields_ = [
+        ("counters", ctypes.c_void_p),
+        ("history", ctypes.c_void_p),
+    ]
+
+
 class AnnealParams(ctypes.Structure):
     _fields_ = [
         ("replicas", ctypes.c_int32),
@@ -30,6 +37,9 @@ class AnnealParams(ctypes.Structure):
         ("target_energy", ctypes.c_int64),
         ("block_columns", ctypes.c_int32),
         ("operand_format", ctypes.c_int32),
+        ("start_cycle", ctypes.c_int32),
+        ("stop_cycle", ctypes.c_int32),
+        ("resume", ctypes.POINTER(AnnealState)),
     ]
 
 
@@ -39,6 +49,7 @@ class AnnealOutputs(ctypes.Structure):
         ("first_hit", ctypes.c_void_p),
         ("energy_trace", ctypes.c_void_p),
         ("final_is", ctypes.c_void_p),
+        ("checkpoint", ctypes.POINTER(AnnealState)),
     ]
 
 

@@ -90,11 +90,21 @@ def ssqa_create_problem(h, J, device: int = 0) -> Problem:
 
 
 @dataclass
+class AnnealState:
+    """State of an anneal after ``cycle`` cycles (ssqa_anneal_state): counters int8 [T, R, N] and the
+    delayed spins sigma(t - s), s = 1..d, bit-packed as int32 [T, R, d, ceil(N / 32)] (None when d = 0)."""
+    counters: "object"
+    history: "object | None"
+    cycle: int
+
+
+@dataclass
 class AnnealResult:
     best_energy: "object"          # torch int64 [T] on the device
     first_hit: "object"            # torch int32 [T]
     energy_trace: "object | None"  # torch int32 [SC + 1, T, R]
     final_is: "object | None"      # torch int8 [T, R, N]
+    checkpoint: "AnnealState | None" = None
 
 
 def _stream_handle(stream):
@@ -134,32 +144,63 @@ def _params(*, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, see
     return p, (jperp, i0)          # keep the arrays alive as long as the struct
 
 
+def _state_struct(state: "AnnealState | None"):
+    if state is None:
+        return None
+    st = _lib.AnnealState()
+    st.counters = state.counters.data_ptr()
+    st.history = state.history.data_ptr() if state.history is not None else None
+    return st
+
+
 def _outputs(out: AnnealResult):
     o = _lib.AnnealOutputs()
     o.best_energy = out.best_energy.data_ptr()
     o.first_hit = out.first_hit.data_ptr()
     o.energy_trace = out.energy_trace.data_ptr() if out.energy_trace is not None else None
     o.final_is = out.final_is.data_ptr() if out.final_is is not None else None
-    return o
+    ck = _state_struct(out.checkpoint)
+    if ck is not None:
+        o.checkpoint = ctypes.pointer(ck)
+    return o, ck
 
 
 def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
                 noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
                 trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, block_columns: int = 0,
-                operand_format: int = 0, stream=None, out: AnnealResult | None = None) -> AnnealResult:
+                operand_format: int = 0, stream=None, out: AnnealResult | None = None,
+                stop_cycle: int = 0, resume: "AnnealState | None" = None, checkpoint: bool = False) -> AnnealResult:
     """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
-    current stream).  ``out`` may carry preallocated outputs of the right shapes."""
+    current stream).  ``out`` may carry preallocated outputs of the right shapes.
+
+    Checkpoint / resume: ``checkpoint=True`` returns the state after the last cycle run (``stop_cycle``,
+    or all ``cycles``) in ``result.checkpoint``; ``resume=state`` continues from it (pass the interrupted
+    run's ``out`` as well, since best energies and first hits carry over)."""
+    import torch
     lib = _lib.load()
     if out is None:
         out = _alloc_outputs(problem, trials, replicas, cycles, trace, final_is)
+    if checkpoint:
+        dev = out.best_energy.device
+        words = (problem.n + 31) // 32
+        out.checkpoint = AnnealState(
+            counters=torch.empty((trials, replicas, problem.n), dtype=torch.int8, device=dev),
+            history=(torch.empty((trials, replicas, delay, words), dtype=torch.int32, device=dev) if delay > 0
+                     else None),
+            cycle=stop_cycle if stop_cycle else cycles)
     p, keep = _params(replicas=replicas, trials=trials, cycles=cycles, jperp=jperp, i0=i0, alpha=alpha,
                       noise_amp=noise_amp, delay=delay, seed=seed, coupling_mode=coupling_mode, target=target,
                       cycles_per_launch=cycles_per_launch, block_columns=block_columns,
                       operand_format=operand_format)
-    o = _outputs(out)
+    p.stop_cycle = int(stop_cycle)
+    rs = _state_struct(resume)
+    if resume is not None:
+        p.start_cycle = int(resume.cycle)
+        p.resume = ctypes.pointer(rs)
+    o, ck = _outputs(out)
     _check(lib.ssqa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
            "ssqa_anneal")
-    del keep
+    del keep, rs, ck
     return out
 
 
@@ -186,7 +227,7 @@ class Batch:
             res = _alloc_outputs(prob, kw["trials"], kw["replicas"], kw["cycles"], trace, final_is)
             p, keep = _params(**kw)
             params[i] = p
-            outs[i] = _outputs(res)
+            outs[i] = _outputs(res)[0]
             handles[i] = prob.handle
             self.results.append(res)
             self._keep.append(keep)

@@ -304,6 +304,16 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     const ssqa_status st = check_params(prob, pa, out);
     if (st != SSQA_OK) return st;
     const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
+    const int t0 = pa->start_cycle;
+    const int t1 = pa->stop_cycle == 0 ? SC : pa->stop_cycle;
+    if (t0 < 0 || t0 > SC) return fail(SSQA_EINVAL, "start_cycle = %d outside [0, cycles = %d]", t0, SC);
+    if (t1 < t0 || t1 > SC || (t1 == t0 && t1 != SC))
+        return fail(SSQA_EINVAL, "stop_cycle = %d must lie in (start_cycle, cycles] (or be 0)", pa->stop_cycle);
+    if (t0 > 0 && (!pa->resume || !pa->resume->counters || (pa->delay > 0 && !pa->resume->history)))
+        return fail(SSQA_EINVAL, "start_cycle > 0 needs a resume state with counters (and history when d > 0)");
+    const ssqa_anneal_state* ckpt = out->checkpoint;
+    if (ckpt && (!ckpt->counters || (pa->delay > 0 && !ckpt->history)))
+        return fail(SSQA_EINVAL, "checkpoint needs counters (and history when d > 0)");
 
     DeviceGuard guard(prob->device);
     if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
@@ -328,19 +338,28 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     if (e == hipSuccess && SC > 0) e = hipMemcpyAsync(d_i0, pa->i0, (size_t)SC * 4, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host schedules may be freed on return
 
+    if (e == hipSuccess && t0 > 0)
+        e = launch_import_state(pa->resume->counters, pa->resume->history, prob->dev.n, np, R, T, tpw, nb, pa->delay,
+                                is_state, hist, stream);
     if (e == hipSuccess) {
         SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist, nb, tpw);
-        const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(SC, 1);
-        int t = 0;
+        const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(t1 - t0, 1);
+        int t = t0;
         do {
             a.t_begin = t;
-            a.t_end = std::min(SC, t + chunk);
+            a.t_end = std::min(t1, t + chunk);
             a.final_pass = (a.t_end == SC) ? 1 : 0;
+            a.save_hist = (!a.final_pass || ckpt) ? 1 : 0;
             e = launch_sweep(a, n_wg, stream);
             t = a.t_end;
-        } while (e == hipSuccess && t < SC);
+        } while (e == hipSuccess && t < t1);
         if (e == hipSuccess && out->final_is)
             e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, out->final_is, stream);
+        if (e == hipSuccess && ckpt) {
+            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, ckpt->counters, stream);
+            if (e == hipSuccess && pa->delay > 0)
+                e = launch_export_history(hist, prob->dev.n, np, R, T, tpw, nb, pa->delay, ckpt->history, stream);
+        }
     }
     if (is_state) (void)hipFreeAsync(is_state, stream);
     if (hist) (void)hipFreeAsync(hist, stream);
@@ -373,6 +392,9 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
             return fail(st, "anneal %d: %s", i, msg.c_str());
         }
         if (params[i].cycles_per_launch != 0) return fail(SSQA_EINVAL, "anneal %d: cycles_per_launch must be 0", i);
+        if (params[i].start_cycle != 0 || (params[i].stop_cycle != 0 && params[i].stop_cycle != params[i].cycles) ||
+            outputs[i].checkpoint)
+            return fail(SSQA_EINVAL, "anneal %d: start_cycle, stop_cycle and checkpoint are for ssqa_anneal", i);
         nbs[i] = block_columns(p, &params[i]);
         tpw[i] = nbs[i] / params[i].replicas;
         n_wg[i] = (params[i].trials + tpw[i] - 1) / tpw[i];

@@ -70,6 +70,7 @@ struct SweepArgs {
     int32_t t_begin;        // first cycle of this launch (absolute)
     int32_t t_end;          // cycles [t_begin, t_end) are updated in this launch
     int32_t final_pass;     // evaluate H_p at t_end as well (last launch of a run)
+    int32_t save_hist;      // write sigma(t_end - s), s = 1..d, to hist_state at the end (for a resume)
     int32_t delay;
     int32_t alpha;
     int32_t noise_amp;
@@ -103,6 +104,12 @@ hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
 // one kernel variant; the LDS size is taken for the largest padded N and delay among them.
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
                               int variant, hipStream_t stream);
+// Public anneal state (ssqa_anneal_state) <-> the sweep's internal layout of one plain anneal.
+hipError_t launch_import_state(const int8_t* counters, const uint32_t* history, int32_t n, int32_t np, int32_t R,
+                               int32_t T, int32_t tpw, int32_t nb, int32_t delay, int8_t* is_state,
+                               uint32_t* hist_state, hipStream_t stream);
+hipError_t launch_export_history(const uint32_t* hist_state, int32_t n, int32_t np, int32_t R, int32_t T,
+                                 int32_t tpw, int32_t nb, int32_t delay, uint32_t* history, hipStream_t stream);
 hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, int32_t R, int32_t T,
                                 int32_t tpw, int32_t nb, int8_t* out, hipStream_t stream);
 hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t cols, int64_t* energies,

@@ -167,6 +167,8 @@ ssqa_status ssqa_server_submit(ssqa_server_t s, const ssqa_request* req, int64_t
     if (pa.cycles < 0 || pa.replicas < 1 || pa.trials < 1 || (pa.cycles > 0 && (!pa.jperp || !pa.i0)))
         return fail(SSQA_EINVAL, "bad anneal parameters");
     if (pa.cycles_per_launch != 0) return fail(SSQA_EINVAL, "cycles_per_launch must be 0 for served requests");
+    if (pa.start_cycle != 0 || (pa.stop_cycle != 0 && pa.stop_cycle != pa.cycles))
+        return fail(SSQA_EINVAL, "start_cycle and stop_cycle must be 0 for served requests");
     if (req->early_exit != 0 && req->early_exit != 1) return fail(SSQA_EINVAL, "early_exit must be 0 or 1");
     auto r = std::make_unique<Request>();
     r->id = s->next_id++;
@@ -267,6 +269,7 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
         a.t_begin = r->cycle;
         a.t_end = std::min(r->params.cycles, r->cycle + K);
         a.final_pass = a.t_end == r->params.cycles ? 1 : 0;
+        a.save_hist = a.final_pass ? 0 : 1;
         s->items[i] = a;
         updates += (double)r->n * r->params.replicas * r->params.trials * (a.t_end - a.t_begin);
         const int v = sweep_variant(a.fast != 0, a.mode, a.nb, a.fp4 != 0);

@@ -678,7 +678,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             a.first_hit[b] = hit_l[lb];
         }
     }
-    if (!a.final_pass && a.delay > 0) {
+    if (a.save_hist && a.delay > 0) {
         for (int u = tid; u < kNB * words; u += kThreads) {
             const int c = u / words;
             const int w = u - c * words;
@@ -758,6 +758,50 @@ __global__ void prepare_fp4_kernel(const int32_t* J32, int32_t n, int32_t np, in
         int nib;
         const size_t off = tiled_offset_fp4(i, j0, kp4, &nib);
         J4[off] = (uint8_t)(fp4_code(v0) | (fp4_code(v1) << 4));
+    }
+}
+
+// Public state -> internal layout, one workgroup per (trial, replica) column: counters of real spins
+// (padded spins start at 0; they never reach a real spin) and the delayed bit planes in spread order.
+__global__ void import_state_kernel(const int8_t* counters, const uint32_t* history, int32_t n, int32_t np,
+                                    int32_t R, int32_t T, int32_t tpw, int32_t nb, int32_t delay, int8_t* is_state,
+                                    uint32_t* hist_state) {
+    const int col = blockIdx.x;   // b * R + k
+    const int b = col / R;
+    const int k = col - b * R;
+    if (b >= T) return;
+    const int wg = b / tpw;
+    const int lc = (b - wg * tpw) * R + k;
+    int8_t* dst = is_state + ((size_t)wg * nb + lc) * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = i < n ? counters[(size_t)col * n + i] : 0;
+    const int words = np / 32, W = (n + 31) / 32;
+    for (int u = threadIdx.x; u < delay * words; u += blockDim.x) {
+        const int s = u / words;
+        const int w = u - s * words;
+        const uint32_t natural = w < W ? history[((size_t)col * delay + s) * W + w] : 0u;
+        hist_state[(((size_t)wg * delay + s) * nb + lc) * words + w] = spread_bits(natural);
+    }
+}
+
+// Internal delayed bit planes -> public history in natural bit order (bits past N cleared).
+__global__ void export_history_kernel(const uint32_t* hist_state, int32_t n, int32_t np, int32_t R, int32_t T,
+                                      int32_t tpw, int32_t nb, int32_t delay, uint32_t* history) {
+    const int col = blockIdx.x;
+    const int b = col / R;
+    const int k = col - b * R;
+    if (b >= T) return;
+    const int wg = b / tpw;
+    const int lc = (b - wg * tpw) * R + k;
+    const int words = np / 32, W = (n + 31) / 32;
+    for (int u = threadIdx.x; u < delay * W; u += blockDim.x) {
+        const int s = u / W;
+        const int w = u - s * W;
+        const uint32_t spread = hist_state[(((size_t)wg * delay + s) * nb + lc) * words + w];
+        uint32_t natural = 0;
+        for (int o = 0; o < 32; ++o) natural |= ((spread >> bitpos(o)) & 1u) << o;
+        const int valid = n - 32 * w;
+        if (valid < 32) natural &= (1u << valid) - 1u;
+        history[((size_t)col * delay + s) * W + w] = natural;
     }
 }
 
@@ -922,6 +966,21 @@ hipError_t launch_sweep(const SweepArgs& a, int n_wg, hipStream_t stream) {
 #undef SSQA_LAUNCH_ONE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_import_state(const int8_t* counters, const uint32_t* history, int32_t n, int32_t np, int32_t R,
+                               int32_t T, int32_t tpw, int32_t nb, int32_t delay, int8_t* is_state,
+                               uint32_t* hist_state, hipStream_t stream) {
+    hipLaunchKernelGGL(import_state_kernel, dim3(T * R), dim3(256), 0, stream, counters, history, n, np, R, T, tpw,
+                       nb, delay, is_state, hist_state);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_history(const uint32_t* hist_state, int32_t n, int32_t np, int32_t R, int32_t T,
+                                 int32_t tpw, int32_t nb, int32_t delay, uint32_t* history, hipStream_t stream) {
+    hipLaunchKernelGGL(export_history_kernel, dim3(T * R), dim3(256), 0, stream, hist_state, n, np, R, T, tpw, nb,
+                       delay, history);
     return hipGetLastError();
 }
 

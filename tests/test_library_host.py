@@ -149,3 +149,35 @@ def test_sa_accept_threshold_matches_oracle_bit_for_bit(lib):
     for x in np.linspace(0.0, 700.0, 5001):
         assert lib.ssqa_sa_accept_threshold(1, float(x)) == sa.accept_threshold(1, float(x)), x
     assert lib.ssqa_sa_accept_threshold(1, 700.0000001) == 0.0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets the C compiler gives the
+    header's structs (a host C program built with gcc against include/ssqa.h)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    structs = {
+        "ssqa_anneal_state": lib_mod.AnnealState, "ssqa_anneal_params": lib_mod.AnnealParams,
+        "ssqa_anneal_outputs": lib_mod.AnnealOutputs, "ssqa_sa_params": lib_mod.SAParams,
+        "ssqa_sa_outputs": lib_mod.SAOutputs, "ssqa_server_config": lib_mod.ServerConfig,
+        "ssqa_request": lib_mod.Request, "ssqa_request_info": lib_mod.RequestInfo,
+        "ssqa_server_stats_t": lib_mod.ServerStats,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ssqa.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
