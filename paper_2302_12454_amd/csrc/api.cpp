@@ -252,7 +252,7 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     int32_t* J32 = nullptr;
     int32_t* h32 = nullptr;
     const size_t plane_bytes = (size_t)planes * np * np;
-    const int kp4 = (np + 255) / 256 * 256;
+    const int kp4 = fp4_k_extent(np);
     hipError_t e = hipMalloc(&p->J_planes, plane_bytes);
     if (e == hipSuccess && fp4_exact) e = hipMalloc(&p->J_fp4, (size_t)np * kp4 / 2);
     if (e == hipSuccess) e = hipMalloc(&p->rowvec, (size_t)np * 4 * 3);

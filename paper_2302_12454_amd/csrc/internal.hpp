@@ -43,6 +43,13 @@ __host__ __device__ inline size_t tiled_offset_fp4(int i, int j, int kp4, int* n
     return ((size_t)(r * nsteps + s) * 8 + ai) * 1024 + (size_t)(g * 16 + slot) * 16 + 4 * d + m;
 }
 
+// K extent of the fp4 copy of J: np rounded up to a multiple of 256, and at least 512, so that the sweep's
+// K loop always has four or more steps of 128 (its software pipeline has one shape for every size).
+inline int fp4_k_extent(int np) {
+    const int k = (np + 255) / 256 * 256;
+    return k < 512 ? 512 : k;
+}
+
 // Device-side description of one problem.
 struct DeviceProblem {
     int32_t n;          // spins N
@@ -51,7 +58,7 @@ struct DeviceProblem {
     const int8_t* J;    // [P][np * np] in the fragment-tiled layout of tiled_offset, zero padded
     const uint8_t* J4;  // fp4 (e2m1) copy of J in the layout of tiled_offset_fp4 when every J_ij is exactly
                         // representable (0, +-1, +-2, +-3, +-4, +-6), else nullptr
-    int32_t kp4;        // K extent of the fp4 copy: np rounded up to a multiple of 256
+    int32_t kp4;        // K extent of the fp4 copy (fp4_k_extent)
     const int32_t* h;   // [np], zero padded
     const int32_t* hr;  // [np]: h_i - sum_j J_ij   (field offset for x = (sigma + 1) / 2)
     const int32_t* er;  // [np]: 2 h_i - sum_j J_ij (energy offset)

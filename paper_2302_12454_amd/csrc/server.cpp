@@ -56,7 +56,7 @@ struct Request {
 // problem turns out to be fp4-exact), row vectors, counters, bit-plane history, outputs, schedules.
 int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa, int nb) {
     const int64_t np = (n + kTileRows - 1) / kTileRows * kTileRows;
-    const int64_t kp4 = (np + 255) / 256 * 256;
+    const int64_t kp4 = fp4_k_extent((int)np);
     const int64_t tpw = nb / pa.replicas;
     const int64_t n_wg = (pa.trials + tpw - 1) / tpw;
     return planes_hint * np * np + np * kp4 / 2 + 12 * np + n_wg * nb * np +

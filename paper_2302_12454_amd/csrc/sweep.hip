@@ -93,7 +93,8 @@ __device__ __forceinline__ void load_fragments(v4i (&A)[8], __amdgpu_buffer_rsrc
 }
 
 // One K step on int8 operands: acc[ai][f] += A[ai] . B[f]; with kReload, A[ai] is refilled from byte offset
-// `next` right behind the MFMAs that read it.
+// `next` right behind the MFMAs that read it.  The scheduling barrier after each row block keeps that order:
+// left alone, the compiler sinks all the refills to the end of the step, a whole step later than intended.
 template <int kNBF, bool kReload>
 __device__ __forceinline__ void mma_i8(v4i (&A)[8], const v4i (&B)[kNBF], v4i (&acc)[8][kNBF],
                                        __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
@@ -102,6 +103,7 @@ __device__ __forceinline__ void mma_i8(v4i (&A)[8], const v4i (&B)[kNBF], v4i (&
 #pragma unroll
         for (int f = 0; f < kNBF; ++f) acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], B[f], acc[ai][f], 0, 0, 0);
         if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -110,7 +112,7 @@ __device__ __forceinline__ v4f mfma_fp4(const v4i& a, const v4i& b, const v4f& c
     return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(widen(a), widen(b), c, 4, 4, 0, 128, 0, 127);
 }
 
-// One K step on fp4 operands.
+// One K step on fp4 operands, scheduled as mma_i8.
 template <int kNBF, bool kReload>
 __device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (&acc)[8][kNBF],
                                         __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
@@ -120,6 +122,7 @@ __device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (
         for (int f = 0; f < kNBF; ++f)
             acc[ai][f] = mfma_fp4(A[ai], B[f], acc[ai][f]);
         if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -340,8 +343,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps tile offsets scalar
-    const int col16 = lane & 15;
-    const int g = lane >> 4;
     const int ntiles = np / kTileRows;
     const int nsteps = np / kStepK;
     const int R = a.R;
@@ -473,54 +474,65 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             v4i acc[8][kNBF];
             // This lane's counters of the tile, fetched during the last K steps for the epilogue.
             v4i cnt[kNBF][2];
-            int8_t* is_lane = is_wg + (size_t)col16 * np + tile * kTileRows + 32 * g;
-            const int voff = lane * 16;
+            // Lane-derived addresses are rebuilt per tile from a laundered lane index: held across the
+            // epilogue they would be spilled, and reloading them in front of the K loop forces a wait for all
+            // J loads in flight at the head of every K step.
+            int tl = lane;
+            asm volatile("" : "+v"(tl));
+            const int tcol = tl & 15;
+            const int tg = tl >> 4;
+            int8_t* is_lane = is_wg + (size_t)tcol * np + tile * kTileRows + 32 * tg;
+            const int voff = tl * 16;
             if constexpr (kFp4) {
                 // Field product on the fp4 copy of J: K steps of 128 with J scaled by 2, fp32 accumulators that
                 // start from the staged per-row constant (1.5 * 2^23 plus an integer).  Every partial sum is
                 // 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any summation order and
                 // its bits are 0x4B400000 plus that integer.
                 v4f accf[8][kNBF];
-                const int ns = a.prob.kp4 / 128;          // even, >= 2
-                const uint32_t* bsrc = pl_cur + col16 * cstride;
-                const int wlast = words - 1;
+                const int ns = a.prob.kp4 / 128;          // even, >= 4
+                // Word 4 s + g of the lane's column for K step s.  When kp4 > np the last steps read up to
+                // (kp4 - np) / 32 - 1 words past the column's slot (into the next column, or past the last
+                // plane into the noise area): J is zero for those K, so the bits read there do not matter.
+                const uint32_t* bsrc = pl_cur + tcol * cstride + tg;
                 const int tile_off = tile * ns * 8 * 1024;
                 v4i A0[8], A1[8];
                 uint32_t bw[kNBF];
                 load_fragments(A0, j4rsrc, voff, tile_off);
                 load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
 #pragma unroll
-                for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(g, wlast)];
+                for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
                 auto next_b = [&](int s) {
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + min(4 * s + g, wlast)];
+                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 4 * s];
                 };
                 auto expand = [&](v4i (&B)[kNBF]) {
 #pragma unroll
                     for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
                 };
+                // ns >= 4.  The J loads in flight at the head of the steady loop are the same, in the same order, on
+                // entry and around the loop (A0 of step s + 2, then A1 of step s + 3), and every path into the loop
+                // issues the same loads: otherwise the compiler waits for every load in flight at the head of each
+                // iteration and the prefetch is lost.
+                v4i B[kNBF];
                 {
                     // Step 0 starts every accumulator of row block ai from the staged constants.
-                    v4i B[kNBF];
                     expand(B);
                     next_b(1);
 #pragma unroll
                     for (int ai = 0; ai < 8; ++ai) {
-                        const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * g + 4 * ai));
+                        const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
 #pragma unroll
                         for (int f = 0; f < kNBF; ++f) accf[ai][f] = mfma_fp4(A0[ai], B[f], start);
-                        if (ns > 2) A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
-                    }
-                    if (ns > 2) {
-                        expand(B);
-                        next_b(2);
-                        mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
+                        A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
+                expand(B);
+                next_b(2);
+                mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
                 // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
                 for (int s = 2; s < ns - 2; s += 2) {
-                    v4i B[kNBF];
                     expand(B);
                     next_b(s + 1);
                     mma_fp4<kNBF, true>(A0, B, accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
@@ -528,20 +540,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                     next_b(s + 2);
                     mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
                 }
-                {
-                    // The last two steps (for ns = 2 only the second: step 0 above was the first): no J left
-                    // to fetch; the next tile's row vectors and the epilogue's counters are fetched instead.
-                    v4i B[kNBF];
-                    if (ns > 2) {
-                        expand(B);
-                        next_b(ns - 1);
-                        mma_fp4<kNBF, false>(A0, B, accf, j4rsrc, voff, 0);
-                    }
-                    if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
-                    prefetch_counters(cnt, is_lane, np);
-                    expand(B);
-                    mma_fp4<kNBF, false>(A1, B, accf, j4rsrc, voff, 0);
-                }
+                // The last two steps: no J left to fetch; the next tile's row vectors and the epilogue's counters
+                // are fetched instead.
+                expand(B);
+                next_b(ns - 1);
+                mma_fp4<kNBF, false>(A0, B, accf, j4rsrc, voff, 0);
+                if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
+                prefetch_counters(cnt, is_lane, np);
+                expand(B);
+                mma_fp4<kNBF, false>(A1, B, accf, j4rsrc, voff, 0);
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
@@ -549,8 +556,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             } else {
                 // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
                 // group g ends up with rows 32 g .. 32 g + 31.
-                const uint32_t* bsrc = pl_cur + col16 * cstride + (g >> 1);
-                const int bsh = 4 * (g & 1);
+                const uint32_t* bsrc = pl_cur + tcol * cstride + (tg >> 1);
+                const int bsh = 4 * (tg & 1);
                 uint32_t bw[kNBF];
                 auto next_b = [&](int s) {
 #pragma unroll
