@@ -112,17 +112,33 @@ __device__ __forceinline__ v4f mfma_fp4(const v4i& a, const v4i& b, const v4f& c
     return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(widen(a), widen(b), c, 4, 4, 0, 128, 0, 127);
 }
 
-// One K step on fp4 operands, scheduled as mma_i8.
-template <int kNBF, bool kReload>
-__device__ __forceinline__ void mma_fp4(v4i (&A)[8], const v4i (&B)[kNBF], v4f (&acc)[8][kNBF],
-                                        __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
+// One K step on fp4 operands, column fragment by column fragment.  On entry Bc holds the expanded operand of
+// fragment 0; cur[f] is the bit-plane word of fragment f.  While the 8 MFMAs of fragment f run, the operand of
+// fragment f + 1 (with kNext, after the last fragment, that of the next step's fragment 0 from `next0`) is
+// expanded in their shadow: an fp4 MFMA leaves the SIMD's issue port free for about one VALU instruction, so
+// interleaved one by one the expansion costs almost nothing, while issued as a block it stalls the MFMAs.
+// With kReload, A[ai] is refilled from byte offset `next` right behind its last MFMA.
+template <int kNBF, bool kReload, bool kNext>
+__device__ __forceinline__ void mma_fp4_cols(v4i (&A)[8], v4i& Bc, const uint32_t (&cur)[kNBF], uint32_t next0,
+                                             v4f (&acc)[8][kNBF], __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
 #pragma unroll
-    for (int ai = 0; ai < 8; ++ai) {
+    for (int f = 0; f < kNBF; ++f) {
+        v4i Bn = Bc;
+        if (f + 1 < kNBF) Bn = expand_operand_fp4(cur[f + 1]);
+        else if (kNext) Bn = expand_operand_fp4(next0);
 #pragma unroll
-        for (int f = 0; f < kNBF; ++f)
-            acc[ai][f] = mfma_fp4(A[ai], B[f], acc[ai][f]);
-        if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+        for (int ai = 0; ai < 8; ++ai) {
+            acc[ai][f] = mfma_fp4(A[ai], Bc, acc[ai][f]);
+            if (kReload && f == kNBF - 1) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+        }
+#pragma unroll
+        for (int ai = 0; ai < 8; ++ai) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // then one VALU instruction
+            if (kReload && f == kNBF - 1) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // and one J load
+        }
         __builtin_amdgcn_sched_barrier(0);
+        Bc = Bn;
     }
 }
 
@@ -315,36 +331,30 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
     }
 }
 
-// LDS layout of one workgroup (dynamic shared memory, 32-bit words):
-//   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring), kNB = 16 kNBF columns
-//   noise   [kWaves][64][4]             one Philox block per column, exchanged inside the wave
-//   e_acc   [kNB]   int32               sum_i sigma_i (2 h_i + F_i) per column, this cycle
-//   hit     [kNB]   int32               per-trial first hit
-//   best    [kNB]   int64               per-trial best energy
-//   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
-//   rows    [kWaves][256] int32         row vectors of each wave's current tile
-// All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
-template <bool kFast, int kMode, int kNBF, bool kFp4>
-__device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
-    constexpr int kNB = 16 * kNBF;
-    extern __shared__ uint32_t lds[];
-    const int np = a.prob.np;
-    const int cstride = plane_stride(np);
-    const int plane_words = kNB * cstride;
-    const int npl = a.delay + 2;
-    uint32_t* planes = lds;
-    uint32_t* noise_lds = lds + npl * plane_words;
-    int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * 64 * 4);
-    int32_t* hit_l = e_acc + kNB;
-    long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
-    uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
-    int32_t* rowst = reinterpret_cast<int32_t*>(colinfo + kNB);      // [kWaves][256]
+// Workgroup state shared by the sweep kernels: the sigma bit-plane ring and the per-column and per-trial
+// accumulators in LDS (layout in sweep_block).
+struct BlockLds {
+    uint32_t* planes;     // [npl][kNB][cstride] sigma bit planes, npl = ring length
+    int npl, plane_words, cstride;
+    int32_t* e_acc;       // [kNB]
+    int32_t* hit_l;       // [kNB]
+    long long* best_l;    // [kNB]
+    uint32_t* colinfo;    // [kNB]
+};
 
+// Column table, per-trial minima and first hits, and sigma(t_begin - s), s = 0..d, with the counters: drawn from
+// the random stream (tag 0) at t_begin = 0, else taken from the counters and the saved history.
+template <int kNB>
+__device__ __forceinline__ void block_init(const SweepArgs& a, const int wg, const BlockLds& L) {
+    uint32_t* planes = L.planes;
+    const int npl = L.npl, plane_words = L.plane_words, cstride = L.cstride;
+    int32_t* e_acc = L.e_acc;
+    int32_t* hit_l = L.hit_l;
+    long long* best_l = L.best_l;
+    uint32_t* colinfo = L.colinfo;
+    const int np = a.prob.np;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps tile offsets scalar
     const int ntiles = np / kTileRows;
-    const int nsteps = np / kStepK;
     const int R = a.R;
     const int b0 = wg * a.tpw;
     const int words = np / 32;
@@ -423,6 +433,108 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         }
     }
     __syncthreads();
+}
+
+// End of cycle t: each replica's H_p (trace), the per-trial minimum and first hit; clears e_acc.
+template <int kNB>
+__device__ __forceinline__ void cycle_close(const SweepArgs& a, const int wg, const int t, const BlockLds& L) {
+    int32_t* e_acc = L.e_acc;
+    int32_t* hit_l = L.hit_l;
+    long long* best_l = L.best_l;
+    const int tid = threadIdx.x;
+    const int R = a.R;
+    const int b0 = wg * a.tpw;
+    __syncthreads();
+
+    // H_p of every replica at cycle t: sum_i sigma_i (2 h_i + F_i) = -2 H_p.
+    if (a.trace) {
+        for (int c = tid; c < a.cols_wg; c += kThreads) {
+            const int lb = c / R;
+            const int b = b0 + lb;
+            if (b < a.T) a.trace[(size_t)t * a.T * R + (size_t)b * R + (c - lb * R)] = -e_acc[c] / 2;
+        }
+    }
+    for (int lb = tid; lb < a.tpw; lb += kThreads) {
+        const int b = b0 + lb;
+        if (b >= a.T) continue;
+        long long m = INT64_MAX;
+        for (int k = 0; k < R; ++k) {
+            const long long e = -(long long)e_acc[lb * R + k] / 2;
+            m = e < m ? e : m;
+        }
+        if (m < best_l[lb]) best_l[lb] = m;
+        if (hit_l[lb] < 0 && a.target != INT64_MIN && m == a.target) hit_l[lb] = t;
+    }
+    __syncthreads();
+    for (int c = tid; c < kNB; c += kThreads) e_acc[c] = 0;
+    __syncthreads();
+}
+
+// End of the launch: per-trial results, and sigma(t_end - s), s = 1..d, for a later launch.
+template <int kNB>
+__device__ __forceinline__ void block_close(const SweepArgs& a, const int wg, const BlockLds& L) {
+    const uint32_t* planes = L.planes;
+    const int npl = L.npl, plane_words = L.plane_words, cstride = L.cstride;
+    const int32_t* hit_l = L.hit_l;
+    const long long* best_l = L.best_l;
+    const int tid = threadIdx.x;
+    const int b0 = wg * a.tpw;
+    const int words = a.prob.np / 32;
+    for (int lb = tid; lb < a.tpw; lb += kThreads) {
+        const int b = b0 + lb;
+        if (b < a.T) {
+            a.best[b] = best_l[lb];
+            a.first_hit[b] = hit_l[lb];
+        }
+    }
+    if (a.save_hist && a.delay > 0) {
+        for (int u = tid; u < kNB * words; u += kThreads) {
+            const int c = u / words;
+            const int w = u - c * words;
+            for (int s = 1; s <= a.delay; ++s) {
+                const int p = ((a.t_end - s) % npl + npl) % npl;
+                a.hist_state[(((size_t)wg * a.delay + (s - 1)) * kNB + c) * words + w] =
+                    planes[p * plane_words + c * cstride + w];
+            }
+        }
+    }
+}
+
+// LDS layout of one workgroup (dynamic shared memory, 32-bit words):
+//   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring), kNB = 16 kNBF columns
+//   noise   [kWaves][64][4]             one Philox block per column, exchanged inside the wave
+//   e_acc   [kNB]   int32               sum_i sigma_i (2 h_i + F_i) per column, this cycle
+//   hit     [kNB]   int32               per-trial first hit
+//   best    [kNB]   int64               per-trial best energy
+//   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
+//   rows    [kWaves][256] int32         row vectors of each wave's current tile
+// All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
+template <bool kFast, int kMode, int kNBF, bool kFp4>
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
+    constexpr int kNB = 16 * kNBF;
+    extern __shared__ uint32_t lds[];
+    const int np = a.prob.np;
+    const int cstride = plane_stride(np);
+    const int plane_words = kNB * cstride;
+    const int npl = a.delay + 2;
+    uint32_t* planes = lds;
+    uint32_t* noise_lds = lds + npl * plane_words;
+    int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * 64 * 4);
+    int32_t* hit_l = e_acc + kNB;
+    long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
+    uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
+    int32_t* rowst = reinterpret_cast<int32_t*>(colinfo + kNB);      // [kWaves][256]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps tile offsets scalar
+    const int ntiles = np / kTileRows;
+    const int nsteps = np / kStepK;
+    const int b0 = wg * a.tpw;
+    int8_t* is_wg = a.is_state + (size_t)wg * kNB * np;
+
+    const BlockLds L{planes, npl, plane_words, cstride, e_acc, hit_l, best_l, colinfo};
+    block_init<kNB>(a, wg, L);
 
     const int P = a.prob.planes;
     // Buffer resource over all J planes (gfx9 raw buffer, byte addressed).
@@ -496,29 +608,27 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 const uint32_t* bsrc = pl_cur + tcol * cstride + tg;
                 const int tile_off = tile * ns * 8 * 1024;
                 v4i A0[8], A1[8];
-                uint32_t bw[kNBF];
+                // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
+                uint32_t w[kNBF], wn[kNBF];
+                auto read_words = [&](uint32_t (&dst)[kNBF], int s) {
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) dst[f] = bsrc[16 * f * cstride + 4 * s];
+                };
                 load_fragments(A0, j4rsrc, voff, tile_off);
                 load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
-#pragma unroll
-                for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride];
+                read_words(w, 0);
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
-                auto next_b = [&](int s) {
-#pragma unroll
-                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 4 * s];
-                };
-                auto expand = [&](v4i (&B)[kNBF]) {
-#pragma unroll
-                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(bw[f]);
-                };
                 // ns >= 4.  The J loads in flight at the head of the steady loop are the same, in the same order, on
                 // entry and around the loop (A0 of step s + 2, then A1 of step s + 3), and every path into the loop
                 // issues the same loads: otherwise the compiler waits for every load in flight at the head of each
                 // iteration and the prefetch is lost.
-                v4i B[kNBF];
+                v4i Bc;
                 {
                     // Step 0 starts every accumulator of row block ai from the staged constants.
-                    expand(B);
-                    next_b(1);
+                    v4i B[kNBF];
+#pragma unroll
+                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand_fp4(w[f]);
+                    read_words(wn, 1);
 #pragma unroll
                     for (int ai = 0; ai < 8; ++ai) {
                         const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
@@ -527,28 +637,24 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                         A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
                         __builtin_amdgcn_sched_barrier(0);
                     }
+                    Bc = expand_operand_fp4(wn[0]);
                 }
-                expand(B);
-                next_b(2);
-                mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
+                read_words(w, 2);
+                mma_fp4_cols<kNBF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
                 // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
                 for (int s = 2; s < ns - 2; s += 2) {
-                    expand(B);
-                    next_b(s + 1);
-                    mma_fp4<kNBF, true>(A0, B, accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
-                    expand(B);
-                    next_b(s + 2);
-                    mma_fp4<kNBF, true>(A1, B, accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
+                    read_words(wn, s + 1);
+                    mma_fp4_cols<kNBF, true, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
+                    read_words(w, s + 2);
+                    mma_fp4_cols<kNBF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
                 }
                 // The last two steps: no J left to fetch; the next tile's row vectors and the epilogue's counters
                 // are fetched instead.
-                expand(B);
-                next_b(ns - 1);
-                mma_fp4<kNBF, false>(A0, B, accf, j4rsrc, voff, 0);
+                read_words(wn, ns - 1);
+                mma_fp4_cols<kNBF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
                 if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
                 prefetch_counters(cnt, is_lane, np);
-                expand(B);
-                mma_fp4<kNBF, false>(A1, B, accf, j4rsrc, voff, 0);
+                mma_fp4_cols<kNBF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
@@ -652,50 +758,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 fused_epilogue<false, kFast, kMode, kNBF, kFp4>(acc, cnt, ctx);
             }
         }
-        __syncthreads();
-
-        // H_p of every replica at cycle t: sum_i sigma_i (2 h_i + F_i) = -2 H_p.
-        if (a.trace) {
-            for (int c = tid; c < a.cols_wg; c += kThreads) {
-                const int lb = c / R;
-                const int b = b0 + lb;
-                if (b < a.T) a.trace[(size_t)t * a.T * R + (size_t)b * R + (c - lb * R)] = -e_acc[c] / 2;
-            }
-        }
-        for (int lb = tid; lb < a.tpw; lb += kThreads) {
-            const int b = b0 + lb;
-            if (b >= a.T) continue;
-            long long m = INT64_MAX;
-            for (int k = 0; k < R; ++k) {
-                const long long e = -(long long)e_acc[lb * R + k] / 2;
-                m = e < m ? e : m;
-            }
-            if (m < best_l[lb]) best_l[lb] = m;
-            if (hit_l[lb] < 0 && a.target != INT64_MIN && m == a.target) hit_l[lb] = t;
-        }
-        __syncthreads();
-        for (int c = tid; c < kNB; c += kThreads) e_acc[c] = 0;
-        __syncthreads();
+        cycle_close<kNB>(a, wg, t, L);
     }
 
-    for (int lb = tid; lb < a.tpw; lb += kThreads) {
-        const int b = b0 + lb;
-        if (b < a.T) {
-            a.best[b] = best_l[lb];
-            a.first_hit[b] = hit_l[lb];
-        }
-    }
-    if (a.save_hist && a.delay > 0) {
-        for (int u = tid; u < kNB * words; u += kThreads) {
-            const int c = u / words;
-            const int w = u - c * words;
-            for (int s = 1; s <= a.delay; ++s) {
-                const int p = ((a.t_end - s) % npl + npl) % npl;
-                a.hist_state[(((size_t)wg * a.delay + (s - 1)) * kNB + c) * words + w] =
-                    planes[p * plane_words + c * cstride + w];
-            }
-        }
-    }
+    block_close<kNB>(a, wg, L);
 }
 
 template <bool kFast, int kMode, int kNBF, bool kFp4>
