@@ -88,9 +88,10 @@ bool fast_epilogue(const ssqa_anneal_params* pa) {
     return i0_max + 2LL * pa->noise_amp + 2 * q_max * (1 + pa->coupling_mode) <= 128;
 }
 
-// Columns per workgroup: the requested width, or 64 when R <= 64 and the bit planes fit in LDS, else 32.
+// Columns per workgroup: the requested width, or 64 when R <= 64 and the bit planes fit in LDS, else 32
+// (plain_layout may widen an automatic 64 to 128).
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
-    if (pa->block_columns == 32 || pa->block_columns == 64) return pa->block_columns;
+    if (pa->block_columns == 32 || pa->block_columns == 64 || pa->block_columns == 128) return pa->block_columns;
     if (pa->replicas <= 64 && sweep_lds_bytes(prob->dev.np, pa->delay, 64) <= 160 * 1024) return 64;
     return 32;
 }
@@ -114,6 +115,12 @@ PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa)
     const int R = pa->replicas, T = pa->trials;
     const int target = 2 * device_cu_count(prob->device);
     int nb = block_columns(prob, pa);
+    // With fp4 operands, 128 columns per workgroup (one per CU, one wave per SIMD with 512 registers) feed each
+    // J fragment to twice as many MFMAs; taken when whole trials fill the block, the blocks still number two
+    // per CU and the bit planes fit in LDS.
+    if (pa->block_columns == 0 && nb == 64 && use_fp4(prob, pa) && 128 % R == 0 &&
+        (T + 128 / R - 1) / (128 / R) >= target && sweep_lds_bytes(prob->dev.np, pa->delay, 128) <= 160 * 1024)
+        return PlainLayout{128, 128 / R, (T + 128 / R - 1) / (128 / R)};
     if (pa->block_columns == 0 && nb == 64 && R <= 32 && (T + 64 / R - 1) / (64 / R) < target) nb = 32;
     const int full = nb / R;
     int tpw = full;
@@ -124,8 +131,10 @@ PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa)
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out) {
     const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
     if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
-    if (pa->block_columns != 0 && pa->block_columns != 32 && pa->block_columns != 64)
-        return fail(SSQA_EINVAL, "block_columns must be 0, 32 or 64");
+    if (pa->block_columns != 0 && pa->block_columns != 32 && pa->block_columns != 64 && pa->block_columns != 128)
+        return fail(SSQA_EINVAL, "block_columns must be 0, 32, 64 or 128");
+    if (pa->block_columns == 128 && !use_fp4(prob, pa))
+        return fail(SSQA_ENOTSUP, "128 columns per workgroup need fp4 operands");
     if (pa->operand_format < 0 || pa->operand_format > 2) return fail(SSQA_EINVAL, "operand_format must be 0, 1 or 2");
     if (pa->operand_format == 2 && !prob->dev.J4)
         return fail(SSQA_ENOTSUP, "fp4 operands requested but J has entries outside {0, +-1, +-2, +-3, +-4, +-6}");
@@ -467,7 +476,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         list_off[v] = work.size();
         list_len[v] = lists[v].size();
         for (const Entry& en : lists[v]) work.push_back(en.code);
-        if (list_len[v] && sweep_lds_bytes(max_np[v], max_delay[v], (v & 1) ? 32 : 64) > 160 * 1024) {
+        if (list_len[v] && sweep_lds_bytes(max_np[v], max_delay[v], variant_columns(v)) > 160 * 1024) {
             ssqa_batch_destroy(b);
             return fail(SSQA_ENOTSUP, "batch needs more than 160 KiB of LDS per workgroup");
         }

@@ -67,7 +67,7 @@ struct DeviceProblem {
 // Arguments of one launch of the persistent sweep kernel.
 struct SweepArgs {
     DeviceProblem prob;
-    int32_t nb;             // columns per workgroup: 64 or 32
+    int32_t nb;             // columns per workgroup: 32, 64 or 128 (fp4 operands only)
     int32_t fp4;            // 1: the field product runs on the fp4 copy of J
     int32_t fast;           // 1: alpha = 1 and max I0 + 2 noise_amp + 2 max |jperp| (1 + mode) <= 128
     int32_t R;              // replicas
@@ -103,9 +103,12 @@ hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t
 hipError_t configure_sweep_kernels();
 // Dynamic LDS of one sweep workgroup for padded size np, delay d and nb columns.
 size_t sweep_lds_bytes(int np, int delay, int nb);
-// Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.
-constexpr int kSweepVariants = 16;
+// Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.  nb = 128
+// exists with fp4 operands only (-1 otherwise).
+constexpr int kSweepVariants = 20;
 int sweep_variant(bool fast, int mode, int nb, bool fp4);
+// Columns per workgroup of a variant.
+int variant_columns(int variant);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
 // items: device array of anneals; work: device list of (item << 16 | column block), n_work entries, all of
 // one kernel variant; the LDS size is taken for the largest padded N and delay among them.

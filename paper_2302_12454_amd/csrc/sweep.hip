@@ -35,7 +35,9 @@ constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * 64;
 
 // Columns per workgroup: kNBF MFMA column fragments of 16 (kNBF = 4: 64 columns, the default; kNBF = 2:
-// 32 columns, for large N where the bit planes of 64 columns would not fit in LDS).
+// 32 columns, for large N where the bit planes of 64 columns would not fit in LDS; kNBF = 8: 128 columns with
+// fp4 operands, one workgroup per CU and one wave per SIMD, whose 512 registers hold the 256 accumulators:
+// each J fragment then feeds twice as many MFMAs).
 
 __device__ __forceinline__ int plane_stride(int np) { return np / 32 + 1; }
 
@@ -273,7 +275,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
         if (kUpdate) {
             up_w = x.pl_del[(info & 0xFFu) * x.cstride + word];
             if (kMode == 1) dn_w = x.pl_del[((info >> 8) & 0xFFu) * x.cstride + word];
-            noise_w = x.noise_lds[(x.wave * 64 + c) * 4 + eg];
+            noise_w = x.noise_lds[(x.wave * (16 * kNBF) + c) * 4 + eg];
             if (kFast) {
                 up_w ^= x.qflip;
                 dn_w ^= x.qflip;
@@ -502,7 +504,7 @@ __device__ __forceinline__ void block_close(const SweepArgs& a, const int wg, co
 
 // LDS layout of one workgroup (dynamic shared memory, 32-bit words):
 //   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring), kNB = 16 kNBF columns
-//   noise   [kWaves][64][4]             one Philox block per column, exchanged inside the wave
+//   noise   [kWaves][kNB][4]            one Philox block per column, exchanged inside the wave
 //   e_acc   [kNB]   int32               sum_i sigma_i (2 h_i + F_i) per column, this cycle
 //   hit     [kNB]   int32               per-trial first hit
 //   best    [kNB]   int64               per-trial best energy
@@ -519,7 +521,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     const int npl = a.delay + 2;
     uint32_t* planes = lds;
     uint32_t* noise_lds = lds + npl * plane_words;
-    int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * 64 * 4);
+    int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * kNB * 4);
     int32_t* hit_l = e_acc + kNB;
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
     uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
@@ -741,14 +743,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             ctx.i0 = i0;
             ctx.alpha = a.alpha;
             if (update) {
-                // One Philox block per column (lane c < kNB computes column c), shared through LDS within
-                // the wave.
-                if (kNB == 64 || lane < kNB) {
-                    const uint32_t mine = colinfo[lane];
+                // One Philox block per column (lane c computes columns c, c + 64, ...), shared through LDS
+                // within the wave.
+                for (int c = lane; c < kNB; c += 64) {
+                    const uint32_t mine = colinfo[c];
                     const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
                                                     (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
-                    *reinterpret_cast<uint4*>(noise_lds + (wave * 64 + lane) * 4) =
-                        uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
+                    *reinterpret_cast<uint4*>(noise_lds + (wave * kNB + c) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -765,14 +766,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 }
 
 template <bool kFast, int kMode, int kNBF, bool kFp4>
-__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, kNBF == 8 ? 1 : 2) void sweep_kernel(SweepArgs a) {
     sweep_block<kFast, kMode, kNBF, kFp4>(a, blockIdx.x);
 }
 
 // Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
 // host in decreasing cost so that the largest blocks start first.
 template <bool kFast, int kMode, int kNBF, bool kFp4>
-__global__ __launch_bounds__(kThreads, 2) void sweep_batch_kernel(const SweepArgs* __restrict__ items,
+__global__ __launch_bounds__(kThreads, kNBF == 8 ? 1 : 2) void sweep_batch_kernel(const SweepArgs* __restrict__ items,
                                                                    const uint32_t* __restrict__ work) {
     const uint32_t w = work[blockIdx.x];
     const SweepArgs a = items[w >> 16];
@@ -960,7 +961,7 @@ hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, 
 
 size_t sweep_lds_bytes(int np, int delay, int nb) {
     const size_t plane_words = (size_t)nb * (np / 32 + 1);
-    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * 64 * 16 + (size_t)nb * 4 * 2 + (size_t)nb * 8 +
+    return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * nb * 16 + (size_t)nb * 4 * 2 + (size_t)nb * 8 +
            (size_t)nb * 4 + (size_t)kWaves * 256 * 4;
 }
 
@@ -985,12 +986,14 @@ hipError_t configure_variant() {
     return e;
 }
 
-// Variant v: bit 3 fast epilogue, bit 2 coupling mode 1, bit 1 fp4 operands, bit 0 32 columns per workgroup.
+// Variant v < 16: bit 3 fast epilogue, bit 2 coupling mode 1, bit 1 fp4 operands, bit 0 32 columns per
+// workgroup (else 64).  v = 16 .. 19: 128 columns, fp4 operands; bit 1 fast epilogue, bit 0 coupling mode 1.
 #define SSQA_FOR_EACH_VARIANT(X) \
     X(0, false, 0, 4, false) X(1, false, 0, 2, false) X(2, false, 0, 4, true) X(3, false, 0, 2, true) \
     X(4, false, 1, 4, false) X(5, false, 1, 2, false) X(6, false, 1, 4, true) X(7, false, 1, 2, true) \
     X(8, true, 0, 4, false) X(9, true, 0, 2, false) X(10, true, 0, 4, true) X(11, true, 0, 2, true) \
-    X(12, true, 1, 4, false) X(13, true, 1, 2, false) X(14, true, 1, 4, true) X(15, true, 1, 2, true)
+    X(12, true, 1, 4, false) X(13, true, 1, 2, false) X(14, true, 1, 4, true) X(15, true, 1, 2, true) \
+    X(16, false, 0, 8, true) X(17, false, 1, 8, true) X(18, true, 0, 8, true) X(19, true, 1, 8, true)
 
 hipError_t configure_sweep_kernels() {
     static hipError_t status = [] {
@@ -1005,12 +1008,15 @@ hipError_t configure_sweep_kernels() {
 }
 
 int sweep_variant(bool fast, int mode, int nb, bool fp4) {
+    if (nb == 128) return fp4 ? 16 + (fast ? 2 : 0) + (mode ? 1 : 0) : -1;
     return (fast ? 8 : 0) + (mode ? 4 : 0) + (fp4 ? 2 : 0) + (nb == 32 ? 1 : 0);
 }
 
+int variant_columns(int variant) { return variant >= 16 ? 128 : (variant & 1) ? 32 : 64; }
+
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,
                               int variant, hipStream_t stream) {
-    const int nb = (variant & 1) ? 32 : 64;
+    const int nb = variant_columns(variant);
     const size_t lds = sweep_lds_bytes(max_np, max_delay, nb);
     const dim3 grid(n_work), block(kThreads);
     switch (variant) {

@@ -191,6 +191,40 @@ def test_block_width_invariance(lib, n, R, T, SC, delay, mode):
     assert_same(narrow, run_oracle(h, J, **kw))
 
 
+@pytest.mark.parametrize("n,R,T,SC,delay,mode,fast", [
+    (300, 16, 20, 30, 1, 0, True),     # byte-parallel epilogue, negative J_perp, ragged tiles (300 of 384 rows)
+    (700, 64, 5, 20, 2, 1, False),     # general epilogue, both ring neighbours, d = 2, trials not filling blocks
+    (129, 1, 200, 15, 0, 0, True),     # 128 single-replica trials per block, one row past a tile
+    (200, 128, 3, 12, 1, 1, True),     # R = 128: one trial fills a block (only this width holds it)
+])
+def test_wide_blocks_fp4(lib, n, R, T, SC, delay, mode, fast):
+    """128 columns per workgroup (fp4 operands, one wave per SIMD, accumulators in the AGPRs) equal the
+    64-column tiling and the oracle bit for bit."""
+    _note(f"case 128-column blocks n={n} R={R} T={T} d={delay} mode={mode}")
+    h, J = random_ising(n, n + 3 * R, h_max=70, j_max=4)   # |J| <= 4: every entry exact in fp4
+    rng = np.random.default_rng(n + R)
+    q = rng.integers(-6, 7, size=SC)
+    i0 = rng.integers(8, 30, size=SC) if fast else rng.integers(5, 100, size=SC)
+    prob = lib.Problem(h, J)
+    assert prob.fp4_exact
+    kw = dict(replicas=R, trials=T, cycles=SC, q=q, i0=i0, alpha=1, noise=9, delay=delay, seed=n, mode=mode)
+    wide = run_gpu(prob, block_columns=128, **kw)
+    if R <= 64:
+        ref64 = run_gpu(prob, block_columns=64, **kw)
+        for key in ("best", "first_hit", "trace", "Is"):
+            assert np.array_equal(wide[key], ref64[key]), key
+    assert_same(wide, run_oracle(h, J, **kw))
+
+
+def test_wide_blocks_need_fp4(lib):
+    h, J = random_ising(100, 5, h_max=10, j_max=9)          # entries of 5, 7, 8, 9 have no fp4 code
+    prob = lib.Problem(h, J)
+    with pytest.raises(lib.SSQAError) as ei:
+        lib.ssqa_anneal(prob, replicas=4, trials=2, cycles=3, jperp=np.zeros(3, np.int32), i0=np.full(3, 20),
+                        alpha=1, noise_amp=4, delay=1, seed=0, block_columns=128)
+    assert ei.value.name == "SSQA_ENOTSUP"
+
+
 def test_large_n_uses_narrow_blocks(lib):
     """N = 6600 (padded 6656): 64-column bit planes exceed LDS, so 32-column blocks run; sampled trials
     against the oracle."""
