@@ -99,6 +99,44 @@ def test_batch_equals_separate_anneals_and_oracle(lib):
     batch.close()
 
 
+def test_batch_with_wide_blocks(lib):
+    """Anneals asking for 128 columns per workgroup (fp4 operands, both epilogues, both coupling modes) in one
+    batch with a 64-column int8 anneal: each equals its separate anneal and the oracle."""
+    import torch
+    _note("case batch with 128-column blocks")
+    rng = np.random.default_rng(12)
+    jobs, models = [], []
+    h, J, e_star = gi_case(6, 21)
+    q, i0, noise = paper_schedules(40, tau=10)
+    jobs.append((lib.Problem(h, J), dict(replicas=16, trials=20, cycles=40, jperp=q, i0=i0, alpha=1,
+                                         noise_amp=noise, delay=1, seed=7, coupling_mode=0, target=e_star,
+                                         block_columns=128)))
+    models.append((h, J))
+    h, J = random_ising(150, 9, h_max=60, j_max=4)
+    jobs.append((lib.Problem(h, J), dict(replicas=32, trials=7, cycles=30, jperp=rng.integers(-5, 6, size=30),
+                                         i0=rng.integers(2, 90, size=30), alpha=2, noise_amp=8, delay=2, seed=8,
+                                         coupling_mode=1, target=None, block_columns=128)))
+    models.append((h, J))
+    h, J = random_ising(90, 10, h_max=60, j_max=9)       # int8 operands, 64 columns
+    jobs.append((lib.Problem(h, J), dict(replicas=8, trials=11, cycles=25, jperp=rng.integers(0, 6, size=25),
+                                         i0=rng.integers(1, 60, size=25), alpha=1, noise_amp=6, delay=0, seed=9,
+                                         coupling_mode=0, target=None)))
+    models.append((h, J))
+    batch = lib.Batch([(p, dict(kw, trace=True, final_is=True)) for p, kw in jobs])
+    results = [_host(r) for r in batch.run()]
+    torch.cuda.synchronize()
+    for i, ((prob, kw), (h, J)) in enumerate(zip(jobs, models)):
+        alone = _host(lib.ssqa_anneal(prob, trace=True, final_is=True, **kw))
+        torch.cuda.synchronize()
+        for key in ("best", "first_hit", "trace", "Is"):
+            assert np.array_equal(results[i][key], alone[key]), (i, key)
+        ref = run_oracle(h, J, replicas=kw["replicas"], trials=kw["trials"], cycles=kw["cycles"], q=kw["jperp"],
+                         i0=kw["i0"], alpha=kw["alpha"], noise=kw["noise_amp"], delay=kw["delay"], seed=kw["seed"],
+                         mode=kw["coupling_mode"], target=kw["target"])
+        assert_same(results[i], ref)
+    batch.close()
+
+
 def test_uneven_gi_batch(lib):
     """Forty GI instances of uneven size (n from 10 to 50, edge probability 0.3-0.7), R = 32, T = 64, in
     one launch: every instance equals its separate anneal; two instances replayed by the oracle."""

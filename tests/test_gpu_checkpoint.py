@@ -42,6 +42,12 @@ def _case(name):
         kw = dict(replicas=8, trials=20, cycles=300, jperp=q, i0=i0, alpha=1, noise_amp=noise, delay=1, seed=4,
                   target=e_star)
         return h, J, kw, 150, (0, 0)
+    if name == "gi6_wide_to_narrow":
+        h, J, e_star = gi_case(6, 5)
+        q, i0, noise = paper_schedules(120, tau=20)
+        kw = dict(replicas=16, trials=24, cycles=120, jperp=q, i0=i0, alpha=1, noise_amp=noise, delay=2, seed=6,
+                  target=e_star)
+        return h, J, kw, 70, (128, 64)
     if name == "ising300_d2_mode1":
         h, J = random_ising(300, 21, h_max=70, j_max=9)
         rng = np.random.default_rng(21)
@@ -58,7 +64,7 @@ def _case(name):
     return h, J, kw, 17, (0, 0)
 
 
-@pytest.mark.parametrize("name", ["gi6_fp4", "ising300_d2_mode1", "ising129_d0"])
+@pytest.mark.parametrize("name", ["gi6_fp4", "gi6_wide_to_narrow", "ising300_d2_mode1", "ising129_d0"])
 def test_checkpoint_resume_equals_uninterrupted(lib, name):
     import torch
     _note(f"case checkpoint/resume {name}")
