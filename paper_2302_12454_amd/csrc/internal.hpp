@@ -187,7 +187,7 @@ struct DeviceGuard {
 
 // Whether an anneal of `prob` with `pa` runs its field product on the fp4 copy of J.
 bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa);
-// Columns per workgroup for an anneal of `prob` with `pa` (64 or 32).
+// Columns per workgroup for an anneal of `prob` with `pa`: the requested 32, 64 or 128, else 64 or 32.
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Full argument check of one anneal; records the reason on failure.
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out);
