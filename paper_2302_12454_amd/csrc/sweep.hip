@@ -437,38 +437,42 @@ __device__ __forceinline__ void block_init(const SweepArgs& a, const int wg, con
     __syncthreads();
 }
 
-// End of cycle t: each replica's H_p (trace), the per-trial minimum and first hit; clears e_acc.
+// End of cycle t: each replica's H_p (trace), the per-trial minimum and first hit; clears e_acc.  Wave w
+// takes trials w, w + kWaves, ...: lane k reads replica k (and k + 64, ...), the minimum is reduced across
+// the wave, and the lanes that read an entry clear it (entries of idle columns are never written).
 template <int kNB>
 __device__ __forceinline__ void cycle_close(const SweepArgs& a, const int wg, const int t, const BlockLds& L) {
     int32_t* e_acc = L.e_acc;
     int32_t* hit_l = L.hit_l;
     long long* best_l = L.best_l;
     const int tid = threadIdx.x;
+    const int ln = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int R = a.R;
     const int b0 = wg * a.tpw;
     __syncthreads();
 
     // H_p of every replica at cycle t: sum_i sigma_i (2 h_i + F_i) = -2 H_p.
-    if (a.trace) {
-        for (int c = tid; c < a.cols_wg; c += kThreads) {
-            const int lb = c / R;
-            const int b = b0 + lb;
-            if (b < a.T) a.trace[(size_t)t * a.T * R + (size_t)b * R + (c - lb * R)] = -e_acc[c] / 2;
-        }
-    }
-    for (int lb = tid; lb < a.tpw; lb += kThreads) {
+    for (int lb = wv; lb < a.tpw; lb += kWaves) {
         const int b = b0 + lb;
-        if (b >= a.T) continue;
         long long m = INT64_MAX;
-        for (int k = 0; k < R; ++k) {
-            const long long e = -(long long)e_acc[lb * R + k] / 2;
+        for (int k = ln; k < R; k += 64) {
+            const int c = lb * R + k;
+            const long long e = -(long long)e_acc[c] / 2;
+            if (b < a.T && a.trace) a.trace[(size_t)t * a.T * R + (size_t)b * R + k] = (int32_t)e;
             m = e < m ? e : m;
+            e_acc[c] = 0;
         }
-        if (m < best_l[lb]) best_l[lb] = m;
-        if (hit_l[lb] < 0 && a.target != INT64_MIN && m == a.target) hit_l[lb] = t;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const long long o = __shfl_xor(m, off);
+            m = o < m ? o : m;
+        }
+        if (ln == 0 && b < a.T) {
+            if (m < best_l[lb]) best_l[lb] = m;
+            if (hit_l[lb] < 0 && a.target != INT64_MIN && m == a.target) hit_l[lb] = t;
+        }
     }
-    __syncthreads();
-    for (int c = tid; c < kNB; c += kThreads) e_acc[c] = 0;
     __syncthreads();
 }
 
