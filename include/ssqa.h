@@ -124,8 +124,10 @@ typedef struct ssqa_anneal_params {
     int64_t target_energy;     /* E* for first_hit, or SSQA_NO_TARGET                           */
     int32_t block_columns;     /* columns (whole trials) per workgroup: 0 = automatic (64 when R <= 64
                                   and the bit planes fit in LDS, else 32; with fp4 operands 128 when
-                                  R divides 128, the 128-column blocks number at least two per CU and
-                                  fit in LDS), or 32 / 64 / 128 (128 needs fp4 operands, else
+                                  R divides 128, the problem pads to at least 1024 rows and the
+                                  planes fit in LDS; for ssqa_anneal also at least 2048 rows in a
+                                  multiple of 512 and at least two 128-column blocks per CU), or
+                                  32 / 64 / 128 (128 needs fp4 operands, else
                                   SSQA_ENOTSUP).  A tiling choice only: results do not depend on it */
     int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when every J_ij is one of
                                   0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J| is below 2^21,

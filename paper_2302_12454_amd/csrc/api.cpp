@@ -107,6 +107,20 @@ int device_cu_count(int device) {
     return counts[device];
 }
 
+// Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
+// block, bit planes that fit in LDS, and at least 1024 padded rows.  With fewer rows the K loop of a tile is
+// short and two 64-column workgroups per CU hide its latency better than one of 128 columns.  A plain
+// anneal (`plain`) also needs at least 2048 rows in a multiple of four 128-row tiles: the four waves of a
+// workgroup take the tiles in turn, and with one wave per SIMD a wave left without a tile in the last
+// round idles its SIMD, where a second 64-column workgroup would fill it.  In a batch the halved J
+// traffic of the many matrices sharing each L2 outweighs that loss.
+static bool wide_blocks_pay(const ssqa_problem* prob, const ssqa_anneal_params* pa, bool plain) {
+    const int np = prob->dev.np;
+    if (plain && (np < 2048 || (np / kTileRows) % 4 != 0)) return false;
+    return pa->block_columns == 0 && block_columns(prob, pa) == 64 && use_fp4(prob, pa) &&
+           128 % pa->replicas == 0 && np >= 1024 && sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
+}
+
 // Layout of a plain anneal.  Packing whole workgroups (as many trials as fit) gives the best J reuse
 // once there are enough workgroups for every CU twice over; a smaller anneal is spread instead (the
 // narrow block when the replicas fit it, and fewer trials per workgroup, leaving columns unused), so
@@ -116,10 +130,8 @@ PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa)
     const int target = 2 * device_cu_count(prob->device);
     int nb = block_columns(prob, pa);
     // With fp4 operands, 128 columns per workgroup (one per CU, one wave per SIMD with 512 registers) feed each
-    // J fragment to twice as many MFMAs; taken when whole trials fill the block, the blocks still number two
-    // per CU and the bit planes fit in LDS.
-    if (pa->block_columns == 0 && nb == 64 && use_fp4(prob, pa) && 128 % R == 0 &&
-        (T + 128 / R - 1) / (128 / R) >= target && sweep_lds_bytes(prob->dev.np, pa->delay, 128) <= 160 * 1024)
+    // J fragment to twice as many MFMAs; taken when wide blocks pay and still number two per CU.
+    if (wide_blocks_pay(prob, pa, true) && (T + 128 / R - 1) / (128 / R) >= target)
         return PlainLayout{128, 128 / R, (T + 128 / R - 1) / (128 / R)};
     if (pa->block_columns == 0 && nb == 64 && R <= 32 && (T + 64 / R - 1) / (64 / R) < target) nb = 32;
     const int full = nb / R;
@@ -404,7 +416,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         if (params[i].start_cycle != 0 || (params[i].stop_cycle != 0 && params[i].stop_cycle != params[i].cycles) ||
             outputs[i].checkpoint)
             return fail(SSQA_EINVAL, "anneal %d: start_cycle, stop_cycle and checkpoint are for ssqa_anneal", i);
-        nbs[i] = block_columns(p, &params[i]);
+        nbs[i] = wide_blocks_pay(p, &params[i], false) ? 128 : block_columns(p, &params[i]);
         tpw[i] = nbs[i] / params[i].replicas;
         n_wg[i] = (params[i].trials + tpw[i] - 1) / tpw[i];
         if (n_wg[i] > 65535) return fail(SSQA_ENOTSUP, "anneal %d needs more than 65535 blocks", i);
@@ -457,7 +469,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
             std::memcpy(&sched[so + std::max(SC, 1)], pa.i0, (size_t)SC * 4);
         }
         so += 2 * (size_t)std::max(SC, 1);
-        items[i] = make_args(problems[i], &pa, &outputs[i], jp, i0, d_is + io, nullptr);
+        items[i] = make_args(problems[i], &pa, &outputs[i], jp, i0, d_is + io, nullptr, nbs[i], tpw[i]);
         items[i].t_begin = 0;
         items[i].t_end = SC;
         items[i].final_pass = 1;

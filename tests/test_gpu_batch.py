@@ -137,6 +137,42 @@ def test_batch_with_wide_blocks(lib):
     batch.close()
 
 
+def test_batch_widens_blocks_from_1024_rows(lib):
+    """The batch picks 128-column blocks by itself for an fp4 anneal of at least 1024 padded rows (R = 16,
+    T = 24: three workgroups of eight trials), and keeps 64 columns below that (N = 841 pads to 896: six
+    workgroups of four trials).  Each anneal still equals its separate anneal and the oracle."""
+    import torch
+    _note("case batch choosing 128-column blocks at N = 1024")
+    jobs, models = [], []
+    for n, seed in ((32, 31), (29, 32)):
+        h, J, e_star = gi_case(n, seed)
+        q, i0, noise = paper_schedules(40, tau=10)
+        prob = lib.Problem(h, J)
+        assert prob.fp4_exact
+        jobs.append((prob, dict(replicas=16, trials=24, cycles=40, jperp=q, i0=i0, alpha=1, noise_amp=noise,
+                                delay=1, seed=13 + n, coupling_mode=0, target=e_star)))
+        models.append((h, J))
+    assert [p.padded for p, _ in jobs] == [1024, 896]
+    alone_blocks = [lib.Batch([j]) for j in jobs]
+    assert [b.blocks for b in alone_blocks] == [3, 6]
+    for b in alone_blocks:
+        b.close()
+    batch = lib.Batch([(p, dict(kw, trace=True, final_is=True)) for p, kw in jobs])
+    assert batch.blocks == 9
+    results = [_host(r) for r in batch.run()]
+    torch.cuda.synchronize()
+    for i, ((prob, kw), (h, J)) in enumerate(zip(jobs, models)):
+        alone = _host(lib.ssqa_anneal(prob, trace=True, final_is=True, **kw))
+        torch.cuda.synchronize()
+        for key in ("best", "first_hit", "trace", "Is"):
+            assert np.array_equal(results[i][key], alone[key]), (i, key)
+        ref = run_oracle(h, J, replicas=kw["replicas"], trials=kw["trials"], cycles=kw["cycles"], q=kw["jperp"],
+                         i0=kw["i0"], alpha=kw["alpha"], noise=kw["noise_amp"], delay=kw["delay"], seed=kw["seed"],
+                         mode=kw["coupling_mode"], target=kw["target"])
+        assert_same(results[i], ref)
+    batch.close()
+
+
 def test_uneven_gi_batch(lib):
     """Forty GI instances of uneven size (n from 10 to 50, edge probability 0.3-0.7), R = 32, T = 64, in
     one launch: every instance equals its separate anneal; two instances replayed by the oracle."""
