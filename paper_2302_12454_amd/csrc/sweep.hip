@@ -144,24 +144,33 @@ __device__ __forceinline__ void mma_fp4_cols(v4i (&A)[8], v4i& Bc, const uint32_
     }
 }
 
-// The 32 int8 counters of this lane in column fragment f (column 16 f + lane % 16).  They are read through
-// the caches like J: a one-wave-per-SIMD epilogue has no other wave to cover their latency, and streaming
-// (nontemporal) loads of them measured 3-5 % slower on the whole anneal despite leaving J alone in L2.  The
-// epilogue writes them back with streaming stores, which nothing reads before the next cycle.
+// The 32 int8 counters of this lane in column fragment f (column 16 f + lane % 16).  With fp4 operands they
+// are read through the caches: the fp4 copy of J leaves room in L2, a one-wave-per-SIMD epilogue has no other
+// wave to cover their latency, and streaming (nontemporal) loads of them measured 3-5 % slower on the whole
+// anneal.  With int8 operands J alone overflows L2, and cached counter loads evict it (3 % slower), so they
+// stream.  The epilogue writes them back with streaming stores, which nothing reads before the next cycle.
+template <bool kFp4>
 __device__ __forceinline__ void load_counters(v4i (&c)[2], const int8_t* is_lane, int np, int f) {
     const v4i* src = reinterpret_cast<const v4i*>(is_lane + (size_t)16 * f * np);
-    c[0] = src[0];
-    c[1] = src[1];
+    if constexpr (kFp4) {
+        c[0] = src[0];
+        c[1] = src[1];
+    } else {
+        c[0] = __builtin_nontemporal_load(src);
+        c[1] = __builtin_nontemporal_load(src + 1);
+    }
 }
 
-// Counters are fetched kCntAhead fragments ahead of their use: those of fragments 0 .. kCntAhead - 1 during
-// the last K steps, that of fragment f + kCntAhead while the epilogue works on fragment f.
-constexpr int kCntAhead = 2;
+// Counters are fetched cnt_ahead fragments ahead of their use: those of fragments 0 .. cnt_ahead - 1 during
+// the last K steps, that of fragment f + cnt_ahead while the epilogue works on fragment f (two with fp4
+// operands, where the cached loads made the deeper prefetch pay; one with int8).
+template <bool kFp4>
+constexpr int cnt_ahead() { return kFp4 ? 2 : 1; }
 
-template <int kNBF>
+template <int kNBF, bool kFp4>
 __device__ __forceinline__ void prefetch_counters(v4i (&cnt)[kNBF][2], const int8_t* is_lane, int np) {
 #pragma unroll
-    for (int f = 0; f < kNBF && f < kCntAhead; ++f) load_counters(cnt[f], is_lane, np, f);
+    for (int f = 0; f < kNBF && f < cnt_ahead<kFp4>(); ++f) load_counters<kFp4>(cnt[f], is_lane, np, f);
 }
 
 // 4 rows of the tile's row vectors: lane l < 32 takes h - rowsum at rows 4 l .. 4 l + 3, lane l >= 32 takes
@@ -271,8 +280,9 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
         int ep = __builtin_popcount(nsig);
         uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
         v4i* is_ptr = reinterpret_cast<v4i*>(x.is_wg + (size_t)c * x.np + row0);
-        if (kUpdate && f + kCntAhead < kNBF)
-            load_counters(cnt[f + kCntAhead], x.is_wg + (size_t)ecol * x.np + row0, x.np, f + kCntAhead);
+        constexpr int kAhead = cnt_ahead<kFp4>();
+        if (kUpdate && f + kAhead < kNBF)
+            load_counters<kFp4>(cnt[f + kAhead], x.is_wg + (size_t)ecol * x.np + row0, x.np, f + kAhead);
         v4i is_lo = cnt[f][0], is_hi = cnt[f][1];
         if (kUpdate) {
             up_w = x.pl_del[(info & 0xFFu) * x.cstride + word];
@@ -670,7 +680,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 read_words(wn, ns - 1);
                 mma_fp4_cols<kNBF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
                 if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
-                prefetch_counters(cnt, is_lane, np);
+                prefetch_counters<kNBF, kFp4>(cnt, is_lane, np);
                 mma_fp4_cols<kNBF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
@@ -729,7 +739,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                         mma_i8<kNBF, false>(A0, B, acc, jrsrc, voff, 0);
                         if (p == 0) {
                             if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
-                            prefetch_counters(cnt, is_lane, np);
+                            prefetch_counters<kNBF, kFp4>(cnt, is_lane, np);
                         }
                         expand(B);
                         mma_i8<kNBF, false>(A1, B, acc, jrsrc, voff, 0);
