@@ -236,6 +236,16 @@ __device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t w, int a) {
     return (bfe_u(w, 4 * a, 4) * 0x00204081u) & 0x01010101u;
 }
 
+// An accumulator value read out of its AGPR where it is used (128-column blocks, whose 256 accumulators live
+// in AGPRs).  Without it the register allocator copies most accumulators to VGPRs during the last K step,
+// which exceeds the VALU slots the MFMAs leave free there and crowds the epilogue into spilling; with it the
+// kernel needs no scratch and the anneal measured 2 % faster.
+__device__ __forceinline__ int agpr_read(int x) {
+    int r;
+    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(r) : "a"(x));
+    return r;
+}
+
 // Twice the field part of the counter input, 2 sum_j J_ij x_j, plus the accumulator's constant offset.
 template <bool kFp4>
 __device__ __forceinline__ int field2(int acc) { return kFp4 ? acc : acc * 2; }
@@ -311,7 +321,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int pos = 8 * j + ai;
-                const int f2 = field2<kFp4>(acc[ai][f][j]);
+                const int f2 = field2<kFp4>(kNBF == 8 ? agpr_read(acc[ai][f][j]) : acc[ai][f][j]);
                 // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
                 ep = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep);
                 if (kUpdate) {
