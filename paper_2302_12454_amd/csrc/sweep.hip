@@ -94,18 +94,32 @@ __device__ __forceinline__ void load_fragments(v4i (&A)[8], __amdgpu_buffer_rsrc
     for (int ai = 0; ai < 8; ++ai) A[ai] = load_j(rsrc, voff, off + ai * 1024);
 }
 
-// One K step on int8 operands: acc[ai][f] += A[ai] . B[f]; with kReload, A[ai] is refilled from byte offset
-// `next` right behind the MFMAs that read it.  The scheduling barrier after each row block keeps that order:
-// left alone, the compiler sinks all the refills to the end of the step, a whole step later than intended.
-template <int kNBF, bool kReload>
-__device__ __forceinline__ void mma_i8(v4i (&A)[8], const v4i (&B)[kNBF], v4i (&acc)[8][kNBF],
-                                       __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
+// One K step on int8 operands, column fragment by column fragment, as the fp4 step below: while the 8 MFMAs
+// of fragment f run, the operand of fragment f + 1 (with kNext, after the last fragment, that of the next
+// step's fragment 0 from `next0`) is expanded in their shadow, one VALU instruction after each MFMA.  With
+// kReload, A[ai] is refilled from byte offset `next` right behind its last MFMA.  `bsh` selects the lane's
+// half of each word.
+template <int kNBF, bool kReload, bool kNext>
+__device__ __forceinline__ void mma_i8_cols(v4i (&A)[8], v4i& Bc, const uint32_t (&cur)[kNBF], uint32_t next0, int bsh,
+                                            v4i (&acc)[8][kNBF], __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
 #pragma unroll
-    for (int ai = 0; ai < 8; ++ai) {
+    for (int f = 0; f < kNBF; ++f) {
+        v4i Bn = Bc;
+        if (f + 1 < kNBF) Bn = expand_operand(cur[f + 1] >> bsh);
+        else if (kNext) Bn = expand_operand(next0 >> bsh);
 #pragma unroll
-        for (int f = 0; f < kNBF; ++f) acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], B[f], acc[ai][f], 0, 0, 0);
-        if (kReload) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+        for (int ai = 0; ai < 8; ++ai) {
+            acc[ai][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ai], Bc, acc[ai][f], 0, 0, 0);
+            if (kReload && f == kNBF - 1) A[ai] = load_j(rsrc, voff, next + ai * 1024);
+        }
+#pragma unroll
+        for (int ai = 0; ai < 8; ++ai) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // then one VALU instruction
+            if (kReload && f == kNBF - 1) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // and one J load
+        }
         __builtin_amdgcn_sched_barrier(0);
+        Bc = Bn;
     }
 }
 
@@ -701,14 +715,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 // group g ends up with rows 32 g .. 32 g + 31.
                 const uint32_t* bsrc = pl_cur + tcol * cstride + (tg >> 1);
                 const int bsh = 4 * (tg & 1);
-                uint32_t bw[kNBF];
-                auto next_b = [&](int s) {
+                // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
+                uint32_t w[kNBF], wn[kNBF];
+                auto read_words = [&](uint32_t (&dst)[kNBF], int s) {
 #pragma unroll
-                    for (int f = 0; f < kNBF; ++f) bw[f] = bsrc[16 * f * cstride + 2 * s];
-                };
-                auto expand = [&](v4i (&B)[kNBF]) {
-#pragma unroll
-                    for (int f = 0; f < kNBF; ++f) B[f] = expand_operand(bw[f] >> bsh);
+                    for (int f = 0; f < kNBF; ++f) dst[f] = bsrc[16 * f * cstride + 2 * s];
                 };
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
@@ -728,32 +739,25 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                     v4i A0[8], A1[8];
                     load_fragments(A0, jrsrc, voff, tile_off);
                     load_fragments(A1, jrsrc, voff, tile_off + 8 * 1024);
-                    next_b(0);
+                    read_words(w, 0);
                     // Drain the first loads here: at the loop head the loads in flight are then exactly the ones
                     // the previous steps issued in fragment order, so each MFMA group waits for its own fragment.
                     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                    v4i Bc = expand_operand(w[0] >> bsh);
                     for (int s = 0; s < nsteps - 2; s += 2) {
-                        v4i B[kNBF];
-                        expand(B);
-                        next_b(s + 1);
-                        mma_i8<kNBF, true>(A0, B, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
-                        expand(B);
-                        next_b(s + 2);
-                        mma_i8<kNBF, true>(A1, B, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
+                        read_words(wn, s + 1);
+                        mma_i8_cols<kNBF, true, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
+                        read_words(w, s + 2);
+                        mma_i8_cols<kNBF, true, true>(A1, Bc, wn, w[0], bsh, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
                     }
-                    {
-                        // the last two steps: no J left to fetch
-                        v4i B[kNBF];
-                        expand(B);
-                        next_b(nsteps - 1);
-                        mma_i8<kNBF, false>(A0, B, acc, jrsrc, voff, 0);
-                        if (p == 0) {
-                            if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
-                            prefetch_counters<kNBF, kFp4>(cnt, is_lane, np);
-                        }
-                        expand(B);
-                        mma_i8<kNBF, false>(A1, B, acc, jrsrc, voff, 0);
+                    // the last two steps: no J left to fetch
+                    read_words(wn, nsteps - 1);
+                    mma_i8_cols<kNBF, false, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, 0);
+                    if (p == 0) {
+                        if (more) rowv_next = fetch_rows<kFp4>(a.prob, tile + kWaves);
+                        prefetch_counters<kNBF, kFp4>(cnt, is_lane, np);
                     }
+                    mma_i8_cols<kNBF, false, false>(A1, Bc, wn, 0u, bsh, acc, jrsrc, voff, 0);
                 }
             }
 
