@@ -229,13 +229,6 @@ __device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
     return r;
 }
 
-// v_perm_b32 selectors that put byte 0 of the second operand at byte j and keep the other bytes of the first.
-__host__ __device__ constexpr uint32_t insert_byte_sel(int j) {
-    uint32_t sel = 0;
-    for (int i = 0; i < 4; ++i) sel |= (uint32_t)(i == j ? 0 : 4 + i) << (8 * i);
-    return sel;
-}
-
 // (a ^ b) + c in one instruction.
 __device__ __forceinline__ int xad_u32(int a, int b, int c) {
     int r;
@@ -301,7 +294,8 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
         const int c = 16 * f + ecol;
         const uint32_t info = x.colinfo[c];
         const uint32_t nsig = ~x.pl_cur[c * x.cstride + word];
-        int ep = __builtin_popcount(nsig);
+        // four independent partial sums (one per byte position j), so that the energy is not one long chain
+        int ep4[4] = {__builtin_popcount(nsig), 0, 0, 0};
         uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
         v4i* is_ptr = reinterpret_cast<v4i*>(x.is_wg + (size_t)c * x.np + row0);
         constexpr int kAhead = cnt_ahead<kFp4>();
@@ -323,6 +317,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
             v4i hq4 = v4i{0, 0, 0, 0};   // fp4: already in the accumulator
             if (kUpdate && !kFp4) hq4 = *reinterpret_cast<const v4i*>(x.rows + 32 * eg + 4 * ai);
             uint32_t isw_new = 0;
+            int nvs[4] = {0, 0, 0, 0};
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
             uint32_t s4 = 0;
             if (kUpdate && kFast) {
@@ -337,7 +332,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
                 const int pos = 8 * j + ai;
                 const int f2 = field2<kFp4>(kNBF == 8 ? agpr_read(acc[ai][f][j]) : acc[ai][f][j]);
                 // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
-                ep = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep);
+                ep4[j] = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep4[j]);
                 if (kUpdate) {
                     const int base = kFp4 ? f2 : f2 + hq4[j];
                     int nv;
@@ -349,10 +344,16 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
                         const int sv = base + t + bfe_i(isw, 8 * j, 8);
                         nv = sv > hi ? x.i0 - x.alpha : (sv < lo ? lo : sv);
                     }
-                    isw_new = __builtin_amdgcn_perm(isw_new, (uint32_t)nv, insert_byte_sel(j));
+                    nvs[j] = nv;
                 }
             }
             if (kUpdate) {
+                // The low bytes of the four new counters into one dword, as a tree of byte permutes (selector byte
+                // 0..3 picks a byte of the second operand, 4..7 of the first, 0x0C gives zero) rather than a chain
+                // of four byte inserts, whose dependences a one-wave SIMD cannot hide.
+                const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)nvs[1], (uint32_t)nvs[0], 0x0C0C0400u);
+                const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)nvs[3], (uint32_t)nvs[2], 0x04000C0Cu);
+                isw_new = p01 | p23;
                 // sign bit of byte j (bit 8 j + 7) -> bit 8 j + a of the plane word
                 negbits |= (isw_new >> (7 - ai)) & (0x01010101u << ai);
                 if (ai < 4) is_lo[ai] = (int)isw_new; else is_hi[ai - 4] = (int)isw_new;
@@ -366,6 +367,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
         // Each lane adds its 32 rows' share: the four lanes of a column meet in the LDS atomic, which needs no
         // lane index (a cross-lane shuffle would need one, and with every register taken the compiler reloads
         // it from scratch, whose wait then also drains the counter stores just issued).
+        const int ep = (ep4[0] + ep4[1]) + (ep4[2] + ep4[3]);
         if (info >> 31) atomicAdd(&x.e_acc[c], ep);
     }
 }
