@@ -627,7 +627,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         uint32_t* pl_next = planes + p_next * plane_words;
 
         // Row vectors of the wave's first tile; later tiles' are fetched during the previous tile's last K steps.
-        v4i rowv_next = fetch_rows<kFp4>(a.prob, wave);
+        // A wave without a tile (fewer tiles than waves) fetches the last tile's instead, so that the load stays
+        // inside the row vectors; it never uses them.
+        v4i rowv_next = fetch_rows<kFp4>(a.prob, wave < ntiles ? wave : ntiles - 1);
         for (int tile = wave; tile < ntiles; tile += kWaves) {
             // Per-row constants of this tile, staged in LDS for the first K step and the epilogue:
             //   fp4:  [0, 128) the accumulator's start, 0x4B400000 + h - rowsum + row_add_h (as fp32 bits),
