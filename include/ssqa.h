@@ -124,9 +124,9 @@ typedef struct ssqa_anneal_params {
     int64_t target_energy;     /* E* for first_hit, or SSQA_NO_TARGET                           */
     int32_t block_columns;     /* columns (whole trials) per workgroup: 0 = automatic (64 when R <= 64
                                   and the bit planes fit in LDS, else 32; with fp4 operands 128 when
-                                  R divides 128, the problem pads to at least 1024 rows and the
-                                  planes fit in LDS; for ssqa_anneal also at least 2048 rows in a
-                                  multiple of 512 and at least two 128-column blocks per CU), or
+                                  R divides 128, the problem pads to at least 1024 rows (1536 for
+                                  ssqa_anneal, which also needs at least two 128-column blocks per
+                                  CU) and the planes fit in LDS), or
                                   32 / 64 / 128 (128 needs fp4 operands, else
                                   SSQA_ENOTSUP).  A tiling choice only: results do not depend on it */
     int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when every J_ij is one of

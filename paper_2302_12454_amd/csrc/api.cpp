@@ -108,17 +108,15 @@ int device_cu_count(int device) {
 }
 
 // Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
-// block, bit planes that fit in LDS, and at least 1024 padded rows.  With fewer rows the K loop of a tile is
-// short and two 64-column workgroups per CU hide its latency better than one of 128 columns.  A plain
-// anneal (`plain`) also needs at least 2048 rows in a multiple of four 128-row tiles: the four waves of a
-// workgroup take the tiles in turn, and with one wave per SIMD a wave left without a tile in the last
-// round idles its SIMD, where a second 64-column workgroup would fill it.  In a batch the halved J
-// traffic of the many matrices sharing each L2 outweighs that loss.
+// block, bit planes that fit in LDS, and at least 1024 padded rows (1536 for a plain anneal, `plain`).  With
+// fewer rows the K loop of a tile is short and two 64-column workgroups per CU hide its latency better than
+// one of 128 columns; a plain anneal, which has the chip to itself, gains from 1536 rows on, a batch, whose
+// many matrices share each L2, already from 1024 (the halved J traffic per MFMA counts for more there).
 static bool wide_blocks_pay(const ssqa_problem* prob, const ssqa_anneal_params* pa, bool plain) {
     const int np = prob->dev.np;
-    if (plain && (np < 2048 || (np / kTileRows) % 4 != 0)) return false;
     return pa->block_columns == 0 && block_columns(prob, pa) == 64 && use_fp4(prob, pa) &&
-           128 % pa->replicas == 0 && np >= 1024 && sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
+           128 % pa->replicas == 0 && np >= (plain ? 1536 : 1024) &&
+           sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
 }
 
 // Layout of a plain anneal.  Packing whole workgroups (as many trials as fit) gives the best J reuse
