@@ -23,6 +23,8 @@
 //  * J with entries beyond int8 is split into P planes; the K loop runs once per plane, most
 //    significant first, scaling the accumulator by 256 in between (exact Horner evaluation).
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -633,177 +635,177 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         v4i rowv_next;
         auto tile_body = [&](auto kF_c, const int tile, const int foff, const bool more, const int next_tile) {
             constexpr int kF = decltype(kF_c)::value;
-                // Per-row constants of this tile, staged in LDS for the first K step and the epilogue:
-                //   fp4:  [0, 128) the accumulator's start, 0x4B400000 + h - rowsum + row_add_h (as fp32 bits),
-                //         [128, 256) h - row_add_h - 0x4B400000, so that start + 2 field + this = 2 h + F;
-                //   int8: [0, 128) h - rowsum + row_add_h, [128, 256) 2 h - rowsum.
-                stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
-                const int32_t* rows_w = rowst + wave * 256;
-                v4i acc[8][kF];
-                // This lane's counters of the tile, fetched during the last K steps for the epilogue.
-                v4i cnt[kF][2];
-                // Lane-derived addresses are rebuilt per tile from a laundered lane index: held across the
-                // epilogue they would be spilled, and reloading them in front of the K loop forces a wait for all
-                // J loads in flight at the head of every K step.
-                int tl = lane;
-                asm volatile("" : "+v"(tl));
-                const int tcol = tl & 15;
-                const int tg = tl >> 4;
-                int8_t* is_lane = is_wg + (size_t)(tcol + 16 * foff) * np + tile * kTileRows + 32 * tg;
-                const int voff = tl * 16;
-                if constexpr (kFp4) {
-                    // Field product on the fp4 copy of J: K steps of 128 with J scaled by 2, fp32 accumulators that
-                    // start from the staged per-row constant (1.5 * 2^23 plus an integer).  Every partial sum is
-                    // 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any summation order and
-                    // its bits are 0x4B400000 plus that integer.
-                    v4f accf[8][kF];
-                    const int ns = a.prob.kp4 / 128;          // even, >= 4
-                    // Word 4 s + g of the lane's column for K step s.  When kp4 > np the last steps read up to
-                    // (kp4 - np) / 32 - 1 words past the column's slot (into the next column, or past the last
-                    // plane into the noise area): J is zero for those K, so the bits read there do not matter.
-                    const uint32_t* bsrc = pl_cur + (tcol + 16 * foff) * cstride + tg;
-                    const int tile_off = tile * ns * 8 * 1024;
+            // Per-row constants of this tile, staged in LDS for the first K step and the epilogue:
+            //   fp4:  [0, 128) the accumulator's start, 0x4B400000 + h - rowsum + row_add_h (as fp32 bits),
+            //         [128, 256) h - row_add_h - 0x4B400000, so that start + 2 field + this = 2 h + F;
+            //   int8: [0, 128) h - rowsum + row_add_h, [128, 256) 2 h - rowsum.
+            stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
+            const int32_t* rows_w = rowst + wave * 256;
+            v4i acc[8][kF];
+            // This lane's counters of the tile, fetched during the last K steps for the epilogue.
+            v4i cnt[kF][2];
+            // Lane-derived addresses are rebuilt per tile from a laundered lane index: held across the
+            // epilogue they would be spilled, and reloading them in front of the K loop forces a wait for all
+            // J loads in flight at the head of every K step.
+            int tl = lane;
+            asm volatile("" : "+v"(tl));
+            const int tcol = tl & 15;
+            const int tg = tl >> 4;
+            int8_t* is_lane = is_wg + (size_t)(tcol + 16 * foff) * np + tile * kTileRows + 32 * tg;
+            const int voff = tl * 16;
+            if constexpr (kFp4) {
+                // Field product on the fp4 copy of J: K steps of 128 with J scaled by 2, fp32 accumulators that
+                // start from the staged per-row constant (1.5 * 2^23 plus an integer).  Every partial sum is
+                // 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any summation order and
+                // its bits are 0x4B400000 plus that integer.
+                v4f accf[8][kF];
+                const int ns = a.prob.kp4 / 128;          // even, >= 4
+                // Word 4 s + g of the lane's column for K step s.  When kp4 > np the last steps read up to
+                // (kp4 - np) / 32 - 1 words past the column's slot (into the next column, or past the last
+                // plane into the noise area): J is zero for those K, so the bits read there do not matter.
+                const uint32_t* bsrc = pl_cur + (tcol + 16 * foff) * cstride + tg;
+                const int tile_off = tile * ns * 8 * 1024;
+                v4i A0[8], A1[8];
+                // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
+                uint32_t w[kF], wn[kF];
+                auto read_words = [&](uint32_t (&dst)[kF], int s) {
+#pragma unroll
+                    for (int f = 0; f < kF; ++f) dst[f] = bsrc[16 * f * cstride + 4 * s];
+                };
+                load_fragments(A0, j4rsrc, voff, tile_off);
+                load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
+                read_words(w, 0);
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
+                // ns >= 4.  The J loads in flight at the head of the steady loop are the same, in the same order, on
+                // entry and around the loop (A0 of step s + 2, then A1 of step s + 3), and every path into the loop
+                // issues the same loads: otherwise the compiler waits for every load in flight at the head of each
+                // iteration and the prefetch is lost.
+                v4i Bc;
+                {
+                    // Step 0 starts every accumulator of row block ai from the staged constants.
+                    v4i B[kF];
+#pragma unroll
+                    for (int f = 0; f < kF; ++f) B[f] = expand_operand_fp4(w[f]);
+                    read_words(wn, 1);
+#pragma unroll
+                    for (int ai = 0; ai < 8; ++ai) {
+                        const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
+#pragma unroll
+                        for (int f = 0; f < kF; ++f) accf[ai][f] = mfma_fp4(A0[ai], B[f], start);
+                        A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    Bc = expand_operand_fp4(wn[0]);
+                }
+                read_words(w, 2);
+                mma_fp4_cols<kF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
+                // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
+                for (int s = 2; s < ns - 2; s += 2) {
+                    read_words(wn, s + 1);
+                    mma_fp4_cols<kF, true, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
+                    read_words(w, s + 2);
+                    mma_fp4_cols<kF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
+                }
+                // The last two steps: no J left to fetch; the next tile's row vectors and the epilogue's counters
+                // are fetched instead.
+                read_words(wn, ns - 1);
+                mma_fp4_cols<kF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
+                if (more) rowv_next = fetch_rows<kFp4>(a.prob, next_tile);
+                prefetch_counters<kF, kFp4>(cnt, is_lane, np);
+                mma_fp4_cols<kF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai)
+#pragma unroll
+                    for (int f = 0; f < kF; ++f) acc[ai][f] = __builtin_bit_cast(v4i, accf[ai][f]);
+            } else {
+                // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
+                // group g ends up with rows 32 g .. 32 g + 31.
+                const uint32_t* bsrc = pl_cur + (tcol + 16 * foff) * cstride + (tg >> 1);
+                const int bsh = 4 * (tg & 1);
+                // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
+                uint32_t w[kF], wn[kF];
+                auto read_words = [&](uint32_t (&dst)[kF], int s) {
+#pragma unroll
+                    for (int f = 0; f < kF; ++f) dst[f] = bsrc[16 * f * cstride + 2 * s];
+                };
+#pragma unroll
+                for (int ai = 0; ai < 8; ++ai)
+#pragma unroll
+                    for (int f = 0; f < kF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
+                for (int p = P - 1; p >= 0; --p) {
+                    if (p < P - 1) {
+#pragma unroll
+                        for (int ai = 0; ai < 8; ++ai)
+#pragma unroll
+                            for (int f = 0; f < kF; ++f) acc[ai][f] = acc[ai][f] * 256;
+                    }
+                    // J is read through a buffer resource (loads past the planes return 0 instead of faulting),
+                    // one contiguous 1 KiB fragment per load, into two A buffers: buffer b holds step s while the
+                    // loads of step s + 2 refill it right behind the MFMAs that read it.
+                    const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
                     v4i A0[8], A1[8];
-                    // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
-                    uint32_t w[kF], wn[kF];
-                    auto read_words = [&](uint32_t (&dst)[kF], int s) {
-    #pragma unroll
-                        for (int f = 0; f < kF; ++f) dst[f] = bsrc[16 * f * cstride + 4 * s];
-                    };
-                    load_fragments(A0, j4rsrc, voff, tile_off);
-                    load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
+                    load_fragments(A0, jrsrc, voff, tile_off);
+                    load_fragments(A1, jrsrc, voff, tile_off + 8 * 1024);
                     read_words(w, 0);
-                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
-                    // ns >= 4.  The J loads in flight at the head of the steady loop are the same, in the same order, on
-                    // entry and around the loop (A0 of step s + 2, then A1 of step s + 3), and every path into the loop
-                    // issues the same loads: otherwise the compiler waits for every load in flight at the head of each
-                    // iteration and the prefetch is lost.
-                    v4i Bc;
-                    {
-                        // Step 0 starts every accumulator of row block ai from the staged constants.
-                        v4i B[kF];
-    #pragma unroll
-                        for (int f = 0; f < kF; ++f) B[f] = expand_operand_fp4(w[f]);
-                        read_words(wn, 1);
-    #pragma unroll
-                        for (int ai = 0; ai < 8; ++ai) {
-                            const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
-    #pragma unroll
-                            for (int f = 0; f < kF; ++f) accf[ai][f] = mfma_fp4(A0[ai], B[f], start);
-                            A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                        Bc = expand_operand_fp4(wn[0]);
-                    }
-                    read_words(w, 2);
-                    mma_fp4_cols<kF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
-                    // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
-                    for (int s = 2; s < ns - 2; s += 2) {
+                    // Drain the first loads here: at the loop head the loads in flight are then exactly the ones
+                    // the previous steps issued in fragment order, so each MFMA group waits for its own fragment.
+                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                    v4i Bc = expand_operand(w[0] >> bsh);
+                    for (int s = 0; s < nsteps - 2; s += 2) {
                         read_words(wn, s + 1);
-                        mma_fp4_cols<kF, true, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
+                        mma_i8_cols<kF, true, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
                         read_words(w, s + 2);
-                        mma_fp4_cols<kF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + (s + 3) * 8 * 1024);
+                        mma_i8_cols<kF, true, true>(A1, Bc, wn, w[0], bsh, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
                     }
-                    // The last two steps: no J left to fetch; the next tile's row vectors and the epilogue's counters
-                    // are fetched instead.
-                    read_words(wn, ns - 1);
-                    mma_fp4_cols<kF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
-                    if (more) rowv_next = fetch_rows<kFp4>(a.prob, next_tile);
-                    prefetch_counters<kF, kFp4>(cnt, is_lane, np);
-                    mma_fp4_cols<kF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
-    #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai)
-    #pragma unroll
-                        for (int f = 0; f < kF; ++f) acc[ai][f] = __builtin_bit_cast(v4i, accf[ai][f]);
-                } else {
-                    // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
-                    // group g ends up with rows 32 g .. 32 g + 31.
-                    const uint32_t* bsrc = pl_cur + (tcol + 16 * foff) * cstride + (tg >> 1);
-                    const int bsh = 4 * (tg & 1);
-                    // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
-                    uint32_t w[kF], wn[kF];
-                    auto read_words = [&](uint32_t (&dst)[kF], int s) {
-    #pragma unroll
-                        for (int f = 0; f < kF; ++f) dst[f] = bsrc[16 * f * cstride + 2 * s];
-                    };
-    #pragma unroll
-                    for (int ai = 0; ai < 8; ++ai)
-    #pragma unroll
-                        for (int f = 0; f < kF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
-                    for (int p = P - 1; p >= 0; --p) {
-                        if (p < P - 1) {
-    #pragma unroll
-                            for (int ai = 0; ai < 8; ++ai)
-    #pragma unroll
-                                for (int f = 0; f < kF; ++f) acc[ai][f] = acc[ai][f] * 256;
-                        }
-                        // J is read through a buffer resource (loads past the planes return 0 instead of faulting),
-                        // one contiguous 1 KiB fragment per load, into two A buffers: buffer b holds step s while the
-                        // loads of step s + 2 refill it right behind the MFMAs that read it.
-                        const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
-                        v4i A0[8], A1[8];
-                        load_fragments(A0, jrsrc, voff, tile_off);
-                        load_fragments(A1, jrsrc, voff, tile_off + 8 * 1024);
-                        read_words(w, 0);
-                        // Drain the first loads here: at the loop head the loads in flight are then exactly the ones
-                        // the previous steps issued in fragment order, so each MFMA group waits for its own fragment.
-                        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-                        v4i Bc = expand_operand(w[0] >> bsh);
-                        for (int s = 0; s < nsteps - 2; s += 2) {
-                            read_words(wn, s + 1);
-                            mma_i8_cols<kF, true, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
-                            read_words(w, s + 2);
-                            mma_i8_cols<kF, true, true>(A1, Bc, wn, w[0], bsh, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
-                        }
-                        // the last two steps: no J left to fetch
-                        read_words(wn, nsteps - 1);
-                        mma_i8_cols<kF, false, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, 0);
-                        if (p == 0) {
-                            if (more) rowv_next = fetch_rows<kFp4>(a.prob, next_tile);
-                            prefetch_counters<kF, kFp4>(cnt, is_lane, np);
-                        }
-                        mma_i8_cols<kF, false, false>(A1, Bc, wn, 0u, bsh, acc, jrsrc, voff, 0);
+                    // the last two steps: no J left to fetch
+                    read_words(wn, nsteps - 1);
+                    mma_i8_cols<kF, false, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, 0);
+                    if (p == 0) {
+                        if (more) rowv_next = fetch_rows<kFp4>(a.prob, next_tile);
+                        prefetch_counters<kF, kFp4>(cnt, is_lane, np);
                     }
+                    mma_i8_cols<kF, false, false>(A1, Bc, wn, 0u, bsh, acc, jrsrc, voff, 0);
                 }
+            }
 
-                // ---------------- fused epilogue ----------------
-                EpilogueCtx ctx;
-                ctx.pl_cur = pl_cur;
-                ctx.pl_del = pl_del;
-                ctx.pl_next = pl_next;
-                ctx.noise_lds = noise_lds;
-                ctx.colinfo = colinfo;
-                ctx.e_acc = e_acc;
-                ctx.is_wg = is_wg;
-                ctx.rows = rows_w;
-                ctx.np = np;
-                ctx.cstride = cstride;
-                ctx.tile = tile;
-                ctx.wave = wave;
-                ctx.lane = lane;
-                ctx.qflip = qflip;
-                ctx.two_n = two_n;
-                ctx.two_q = two_q;
-                ctx.i0 = i0;
-                ctx.alpha = a.alpha;
-                ctx.coff = 16 * foff;
-                ctx.ncols = kNB;
-                if (update) {
-                    // One Philox block per column (lane c computes columns c, c + 64, ...), shared through LDS
-                    // within the wave.
-                    for (int c = 16 * foff + lane; c < 16 * (foff + kF); c += 64) {
-                        const uint32_t mine = colinfo[c];
-                        const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
-                                                        (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
-                        *reinterpret_cast<uint4*>(noise_lds + (wave * kNB + c) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    fused_epilogue<true, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
-                } else {
-                    fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
+            // ---------------- fused epilogue ----------------
+            EpilogueCtx ctx;
+            ctx.pl_cur = pl_cur;
+            ctx.pl_del = pl_del;
+            ctx.pl_next = pl_next;
+            ctx.noise_lds = noise_lds;
+            ctx.colinfo = colinfo;
+            ctx.e_acc = e_acc;
+            ctx.is_wg = is_wg;
+            ctx.rows = rows_w;
+            ctx.np = np;
+            ctx.cstride = cstride;
+            ctx.tile = tile;
+            ctx.wave = wave;
+            ctx.lane = lane;
+            ctx.qflip = qflip;
+            ctx.two_n = two_n;
+            ctx.two_q = two_q;
+            ctx.i0 = i0;
+            ctx.alpha = a.alpha;
+            ctx.coff = 16 * foff;
+            ctx.ncols = kNB;
+            if (update) {
+                // One Philox block per column (lane c computes columns c, c + 64, ...), shared through LDS
+                // within the wave.
+                for (int c = 16 * foff + lane; c < 16 * (foff + kF); c += 64) {
+                    const uint32_t mine = colinfo[c];
+                    const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
+                                                    (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
+                    *reinterpret_cast<uint4*>(noise_lds + (wave * kNB + c) * 4) = uint4{x.v[0], x.v[1], x.v[2], x.v[3]};
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                fused_epilogue<true, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
+            } else {
+                fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
+            }
         
         };
         // Tiles go to the waves in turn.  With 128-column blocks, when whole rounds of the four waves leave one
