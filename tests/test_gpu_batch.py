@@ -140,11 +140,12 @@ def test_batch_with_wide_blocks(lib):
 def test_batch_widens_blocks_from_1024_rows(lib):
     """The batch picks 128-column blocks by itself for an fp4 anneal of at least 1024 padded rows (R = 16,
     T = 24: three workgroups of eight trials), and keeps 64 columns below that (N = 841 pads to 896: six
-    workgroups of four trials).  Each anneal still equals its separate anneal and the oracle."""
+    workgroups of four trials).  N = 1089 pads to 9 tiles, so the tile left over after two rounds of the four
+    waves is split into column halves.  Each anneal still equals its separate anneal and the oracle."""
     import torch
-    _note("case batch choosing 128-column blocks at N = 1024")
+    _note("case batch choosing 128-column blocks at N = 1024 and 1089")
     jobs, models = [], []
-    for n, seed in ((32, 31), (29, 32)):
+    for n, seed in ((32, 31), (29, 32), (33, 33)):
         h, J, e_star = gi_case(n, seed)
         q, i0, noise = paper_schedules(40, tau=10)
         prob = lib.Problem(h, J)
@@ -152,13 +153,13 @@ def test_batch_widens_blocks_from_1024_rows(lib):
         jobs.append((prob, dict(replicas=16, trials=24, cycles=40, jperp=q, i0=i0, alpha=1, noise_amp=noise,
                                 delay=1, seed=13 + n, coupling_mode=0, target=e_star)))
         models.append((h, J))
-    assert [p.padded for p, _ in jobs] == [1024, 896]
+    assert [p.padded for p, _ in jobs] == [1024, 896, 1152]
     alone_blocks = [lib.Batch([j]) for j in jobs]
-    assert [b.blocks for b in alone_blocks] == [3, 6]
+    assert [b.blocks for b in alone_blocks] == [3, 6, 3]
     for b in alone_blocks:
         b.close()
     batch = lib.Batch([(p, dict(kw, trace=True, final_is=True)) for p, kw in jobs])
-    assert batch.blocks == 9
+    assert batch.blocks == 12
     results = [_host(r) for r in batch.run()]
     torch.cuda.synchronize()
     for i, ((prob, kw), (h, J)) in enumerate(zip(jobs, models)):
