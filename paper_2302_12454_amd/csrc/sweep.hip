@@ -810,24 +810,32 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         };
         // Tiles go to the waves in turn.  With 128-column blocks, when whole rounds of the four waves leave one
         // or two tiles over, those are split into column halves (4 fragments, all 128 rows each), one per wave,
-        // so that the last round is shared instead of leaving two or three waves (one per SIMD) idle.
-        const int rounds = ntiles / kWaves, left = ntiles % kWaves;
+        // so that the last round is shared instead of leaving two or three waves (one per SIMD) idle.  Narrower
+        // blocks keep the plain loop (two workgroups per CU fill each other's idle waves).
         constexpr bool kCanSplit = kFp4 && kNBF == 8;
-        const bool split = kCanSplit && (left == 1 || left == 2);
-        const int n_full = split ? rounds : (ntiles - wave + kWaves - 1) / kWaves;
-        const bool has_half = split && wave < 2 * left;
-        const int half_tile = rounds * kWaves + (wave >> 1);
-        // Row vectors of the wave's first tile; later tiles' are fetched during the previous tile's last K steps.
-        // A wave without work fetches the last tile's instead, so that the load stays inside the row vectors.
-        rowv_next = fetch_rows<kFp4>(a.prob, n_full > 0 ? wave : has_half ? half_tile : ntiles - 1);
-        for (int i = 0; i < n_full; ++i) {
-            const int tile = wave + kWaves * i;
-            const bool last_full = i + 1 == n_full;
-            tile_body(std::integral_constant<int, kNBF>{}, tile, 0, !last_full || has_half,
-                      last_full ? half_tile : tile + kWaves);
-        }
         if constexpr (kCanSplit) {
+            const int rounds = ntiles / kWaves, left = ntiles % kWaves;
+            const bool split = left == 1 || left == 2;
+            const int n_full = split ? rounds : (ntiles - wave + kWaves - 1) / kWaves;
+            const bool has_half = split && wave < 2 * left;
+            const int half_tile = rounds * kWaves + (wave >> 1);
+            // Row vectors of the wave's first tile; later tiles' are fetched during the previous tile's last K
+            // steps.  A wave without work fetches the last tile's instead, so that the load stays inside the row
+            // vectors.
+            rowv_next = fetch_rows<kFp4>(a.prob, n_full > 0 ? wave : has_half ? half_tile : ntiles - 1);
+            for (int i = 0; i < n_full; ++i) {
+                const int tile = wave + kWaves * i;
+                const bool last_full = i + 1 == n_full;
+                tile_body(std::integral_constant<int, kNBF>{}, tile, 0, !last_full || has_half,
+                          last_full ? half_tile : tile + kWaves);
+            }
             if (has_half) tile_body(std::integral_constant<int, kNBF / 2>{}, half_tile, (wave & 1) * (kNBF / 2), false, 0);
+        } else {
+            // A wave without a tile (fewer tiles than waves) fetches the last tile's row vectors instead, so that
+            // the load stays inside the row vectors; it never uses them.
+            rowv_next = fetch_rows<kFp4>(a.prob, wave < ntiles ? wave : ntiles - 1);
+            for (int tile = wave; tile < ntiles; tile += kWaves)
+                tile_body(std::integral_constant<int, kNBF>{}, tile, 0, tile + kWaves < ntiles, tile + kWaves);
         }
         cycle_close<kNB>(a, wg, t, L);
     }
