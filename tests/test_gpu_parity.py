@@ -174,6 +174,25 @@ def test_gi50_sampled_trials_full_size(lib):
     assert (tr[hit[ok], np.nonzero(ok)[0]].min(axis=-1) == e_star).all()
 
 
+def test_plain_auto_wide_blocks_with_split_leftover(lib):
+    """N = 1600 GI pads to 13 tiles.  With 2048 trials of R = 32 the plain layout takes 128-column blocks by
+    itself (512 workgroups, at least 1536 rows), and the tile left over after three rounds of the four waves
+    is split into column halves.  Every trial equals the 64-column tiling, and sampled trials the oracle."""
+    _note("case plain N=1600 R=32 T=2048, automatic 128-column blocks with a split leftover tile")
+    h, J, e_star = gi_case(40, 3)
+    q, i0, noise = paper_schedules(60, tau=20)
+    prob = lib.Problem(h, J)
+    assert prob.padded == 1664 and prob.fp4_exact
+    kw = dict(replicas=32, cycles=60, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=9, target=e_star)
+    auto = run_gpu(prob, trials=2048, final_is=False, **kw)
+    narrow = run_gpu(prob, trials=2048, final_is=False, block_columns=64, **kw)
+    for key in ("best", "first_hit", "trace"):
+        assert np.array_equal(auto[key], narrow[key]), key
+    sample = [0, 1027, 2047]
+    ref = run_oracle(h, J, trials=sample, **kw)
+    assert_same(auto, ref, trial_idx=sample, check_is=False)
+
+
 @pytest.mark.parametrize("n,R,T,SC,delay,mode", [(300, 5, 30, 40, 1, 0), (700, 32, 6, 30, 2, 1), (129, 1, 40, 25, 0, 0)])
 def test_block_width_invariance(lib, n, R, T, SC, delay, mode):
     """The tiling choice (32 or 64 columns per workgroup) does not change any result."""
