@@ -217,6 +217,8 @@ def test_block_width_invariance(lib, n, R, T, SC, delay, mode):
     (200, 128, 3, 12, 1, 1, True),     # R = 128: one trial fills a block (only this width holds it)
     (600, 32, 9, 14, 1, 0, True),      # 5 tiles: one round of four waves, then one tile left over
     (1100, 16, 8, 8, 1, 1, False),     # 9 tiles: two rounds, one left over, general epilogue
+    (880, 32, 6, 12, 1, 0, True),      # 7 tiles: one round, then three left over
+    (870, 16, 10, 10, 2, 1, False),    # 7 tiles, general epilogue, both ring neighbours, d = 2
 ])
 def test_wide_blocks_fp4(lib, n, R, T, SC, delay, mode, fast):
     """128 columns per workgroup (fp4 operands, one wave per SIMD, accumulators in the AGPRs) equal the
