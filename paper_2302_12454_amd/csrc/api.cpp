@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -97,14 +98,16 @@ int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
 }
 
 int device_cu_count(int device) {
-    static int counts[64] = {};
+    // Cached per device; host threads may call the library concurrently, so the cache entries are atomic
+    // (a repeated query by a second thread stores the same value).
+    static std::atomic<int> counts[64] = {};
     if (device < 0 || device >= 64) return 256;
-    if (counts[device] == 0) {
-        int v = 0;
+    int v = counts[device].load(std::memory_order_relaxed);
+    if (v == 0) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v < 1) v = 256;
-        counts[device] = v;
+        counts[device].store(v, std::memory_order_relaxed);
     }
-    return counts[device];
+    return v;
 }
 
 // Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
