@@ -264,26 +264,31 @@ def test_large_n_uses_narrow_blocks(lib):
     assert_same(gpu, ref, trial_idx=[0, 9])
 
 
-def test_maximum_n_at_the_lds_limit(lib):
-    """N = 13056, the largest padded size whose bit planes fit in LDS (32-column blocks, d = 1: exactly
-    160 KiB per workgroup), with fp4 and with int8 operands: sampled trials against the oracle.  With d = 2
-    the same problem needs more LDS than a CU has and is refused."""
-    _note("case maximum N=13056 R=4 T=8 SC=4 (fp4 and int8)")
-    h, J = random_ising(13056, 91, h_max=40, j_max=3, density=0.2)
+@pytest.mark.parametrize("n,block_columns,formats", [
+    (13056, 0, (2, 1)),     # 32-column blocks (chosen by themselves), fp4 and int8 operands
+    (6400, 64, (2, 1)),     # 64-column blocks
+    (3072, 128, (2,)),      # 128-column blocks (fp4 only), 24 tiles
+])
+def test_maximum_n_at_the_lds_limit(lib, n, block_columns, formats):
+    """The largest padded size whose bit planes fit in LDS for each block width at d = 1 (the workgroup's
+    LDS is then exactly 160 KiB): sampled trials against the oracle.  With d = 2 the same problem needs more
+    LDS than a CU has and is refused."""
+    _note(f"case maximum N={n} block_columns={block_columns} R=4 T=8 SC=4")
+    h, J = random_ising(n, 91, h_max=40, j_max=3, density=0.2)
     rng = np.random.default_rng(6)
     SC = 4
     q = rng.integers(0, 6, size=SC)
     i0 = np.full(SC, 30)
     prob = lib.Problem(h, J)
-    assert prob.padded == 13056 and prob.fp4_exact
+    assert prob.padded == n and prob.fp4_exact
     kw = dict(replicas=4, cycles=SC, q=q, i0=i0, alpha=1, noise=7, delay=1, seed=4)
     ref = run_oracle(h, J, trials=[0, 7], **kw)
-    for fmt in (2, 1):
-        gpu = run_gpu(prob, trials=8, operand_format=fmt, **kw)
+    for fmt in formats:
+        gpu = run_gpu(prob, trials=8, operand_format=fmt, block_columns=block_columns, **kw)
         assert_same(gpu, ref, trial_idx=[0, 7])
     with pytest.raises(lib.SSQAError) as ei:
         lib.ssqa_anneal(prob, replicas=4, trials=8, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=7, delay=2,
-                        seed=4)
+                        seed=4, block_columns=block_columns)
     assert ei.value.name == "SSQA_ENOTSUP" and "LDS" in str(ei.value)
     del prob
 
