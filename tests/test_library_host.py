@@ -114,6 +114,29 @@ def test_anneal_rejects_null_problem(lib):
     assert lib.ssqa_anneal(None, ctypes.byref(p), ctypes.byref(o), None) == -1
 
 
+def test_batch_and_server_reject_bad_arguments(lib):
+    """The batched and served entry points check their arguments on the host, before any device call."""
+    h = ctypes.c_void_p()
+    assert lib.ssqa_batch_create(0, None, None, None, ctypes.byref(h)) == -1
+    assert b"count" in lib.ssqa_last_error()
+    assert lib.ssqa_batch_create(65536, None, None, None, ctypes.byref(h)) == -1
+    assert lib.ssqa_batch_create(1, None, None, None, None) == -1
+    assert lib.ssqa_batch_create(1, None, None, None, ctypes.byref(h)) == -1
+    assert b"NULL" in lib.ssqa_last_error()
+    assert lib.ssqa_batch_run(None, None) == -1
+    assert lib.ssqa_batch_blocks(None) == 0
+    lib.ssqa_batch_destroy(None)
+    assert lib.ssqa_server_create(None, ctypes.byref(h)) == -1
+    good = dict(device=0, cycles_per_step=100, max_active=64, memory_budget=1 << 30)
+    for field, value, text in (("cycles_per_step", 0, b"cycles_per_step"), ("max_active", 0, b"max_active"),
+                               ("max_active", 65536, b"max_active"), ("memory_budget", 0, b"memory_budget"),
+                               ("device", -1, b"device")):
+        cfg = lib_mod.ServerConfig(**dict(good, **{field: value}))
+        assert lib.ssqa_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1, field
+        assert text in lib.ssqa_last_error(), field
+    assert lib.ssqa_server_step(None, None, None) == -1
+
+
 def test_no_device_is_reported_not_faked(lib):
     """Without a GPU the library reports SSQA_EDEVICE; there is no CPU fallback."""
     import torch
