@@ -15,6 +15,7 @@
 
 #include "internal.hpp"
 #include "philox.hpp"
+#include "work_order.hpp"
 
 using namespace ssqa;
 
@@ -110,8 +111,7 @@ int device_cu_count(int device) {
     return v;
 }
 
-// XCDs (accelerator complexes, each with its own L2) of a device; 1 when the runtime does not report them.
-static int device_xcd_count(int device) {
+int device_xcd_count(int device) {
     static std::atomic<int> counts[64] = {};
     if (device < 0 || device >= 64) return 1;
     int v = counts[device].load(std::memory_order_relaxed);
@@ -120,6 +120,36 @@ static int device_xcd_count(int device) {
         counts[device].store(v, std::memory_order_relaxed);
     }
     return v;
+}
+
+std::vector<WorkItem> xcd_grouped(const std::vector<WorkItem>& sorted, int xcds) {
+    if (xcds < 2 || sorted.empty()) return sorted;
+    std::vector<size_t> starts;   // first item of each anneal
+    for (size_t i = 0; i < sorted.size(); ++i)
+        if (i == 0 || (sorted[i].code >> 16) != (sorted[i - 1].code >> 16)) starts.push_back(i);
+    const size_t groups = starts.size();
+    const size_t g = sorted.size() / groups;
+    for (size_t k = 0; k < groups; ++k) {
+        const size_t end = k + 1 < groups ? starts[k + 1] : sorted.size();
+        if (end - starts[k] != g) return sorted;   // anneals of different item counts: keep the cost order
+    }
+    if (groups < (size_t)xcds) return sorted;
+    std::vector<std::vector<WorkItem>> q(xcds);
+    const size_t full = groups - groups % xcds;
+    for (size_t k = 0; k < full; ++k) {
+        const size_t round = k / xcds, pos = k % xcds;
+        const size_t x = (round % 2 == 0) ? pos : xcds - 1 - pos;
+        q[x].insert(q[x].end(), sorted.begin() + starts[k], sorted.begin() + starts[k] + g);
+    }
+    size_t j = 0;
+    for (size_t i = full * g; i < sorted.size(); ++i, ++j) q[j % xcds].push_back(sorted[i]);
+    // queue lengths are non-increasing in x and differ by at most one, so position k * xcds + x is q[x][k]
+    std::vector<WorkItem> out;
+    out.reserve(sorted.size());
+    for (size_t k = 0; out.size() < sorted.size(); ++k)
+        for (int x = 0; x < xcds; ++x)
+            if (k < q[x].size()) out.push_back(q[x][k]);
+    return out;
 }
 
 // Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
@@ -405,49 +435,6 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     return SSQA_OK;
 }
 
-// One work item of a batch launch: workgroup (code & 0xFFFF) of anneal (code >> 16), with its cost.
-struct BatchItem {
-    double cost;
-    uint32_t code;
-};
-
-// Launch order of a batch's work items for a device whose workgroups go to its XCDs in turn (workgroup b to
-// XCD b mod xcds).  `sorted` holds the items by decreasing cost, each anneal's items together.  When every
-// anneal has the same number of items, whole anneals are dealt to the XCDs (in a snake order over the
-// anneals by decreasing cost, so that the XCDs' totals stay close), and each XCD's items keep decreasing
-// cost.  An XCD then runs the workgroups of few anneals at a time, whose J stays in its L2, instead of a
-// share of every anneal in flight.  The anneals left over after whole rounds of xcds are dealt item by item.
-// Any order gives the same results; this one only changes where J is read from.
-static std::vector<BatchItem> xcd_grouped(const std::vector<BatchItem>& sorted, int xcds) {
-    if (xcds < 2 || sorted.empty()) return sorted;
-    std::vector<size_t> starts;   // first item of each anneal
-    for (size_t i = 0; i < sorted.size(); ++i)
-        if (i == 0 || (sorted[i].code >> 16) != (sorted[i - 1].code >> 16)) starts.push_back(i);
-    const size_t groups = starts.size();
-    const size_t g = sorted.size() / groups;
-    for (size_t k = 0; k < groups; ++k) {
-        const size_t end = k + 1 < groups ? starts[k + 1] : sorted.size();
-        if (end - starts[k] != g) return sorted;   // anneals of different item counts: keep the cost order
-    }
-    if (groups < (size_t)xcds) return sorted;
-    std::vector<std::vector<BatchItem>> q(xcds);
-    const size_t full = groups - groups % xcds;
-    for (size_t k = 0; k < full; ++k) {
-        const size_t round = k / xcds, pos = k % xcds;
-        const size_t x = (round % 2 == 0) ? pos : xcds - 1 - pos;
-        q[x].insert(q[x].end(), sorted.begin() + starts[k], sorted.begin() + starts[k] + g);
-    }
-    size_t j = 0;
-    for (size_t i = full * g; i < sorted.size(); ++i, ++j) q[j % xcds].push_back(sorted[i]);
-    // queue lengths are non-increasing in x and differ by at most one, so position k * xcds + x is q[x][k]
-    std::vector<BatchItem> out;
-    out.reserve(sorted.size());
-    for (size_t k = 0; out.size() < sorted.size(); ++k)
-        for (int x = 0; x < xcds; ++x)
-            if (k < q[x].size()) out.push_back(q[x][k]);
-    return out;
-}
-
 ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
                               const ssqa_anneal_outputs* outputs, ssqa_batch_t* out) {
     g_last_error.clear();
@@ -509,7 +496,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
     std::vector<int32_t> sched(sched_words);
     size_t so = 0, io = 0;
     constexpr int kVariants = kSweepVariants;
-    std::vector<BatchItem> lists[kVariants];
+    std::vector<WorkItem> lists[kVariants];
     int max_np[kVariants] = {}, max_delay[kVariants] = {};
     for (int i = 0; i < count; ++i) {
         const ssqa_anneal_params& pa = params[i];
@@ -537,11 +524,11 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
     size_t list_off[kVariants], list_len[kVariants];
     const int xcds = device_xcd_count(device);
     for (int v = 0; v < kVariants; ++v) {
-        std::stable_sort(lists[v].begin(), lists[v].end(), [](const BatchItem& x, const BatchItem& y) { return x.cost > y.cost; });
+        std::stable_sort(lists[v].begin(), lists[v].end(), [](const WorkItem& x, const WorkItem& y) { return x.cost > y.cost; });
         lists[v] = xcd_grouped(lists[v], xcds);
         list_off[v] = work.size();
         list_len[v] = lists[v].size();
-        for (const BatchItem& en : lists[v]) work.push_back(en.code);
+        for (const WorkItem& en : lists[v]) work.push_back(en.code);
         if (list_len[v] && sweep_lds_bytes(max_np[v], max_delay[v], variant_columns(v)) > 160 * 1024) {
             ssqa_batch_destroy(b);
             return fail(SSQA_ENOTSUP, "batch needs more than 160 KiB of LDS per workgroup");

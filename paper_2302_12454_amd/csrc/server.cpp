@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "work_order.hpp"
 
 using namespace ssqa;
 using namespace ssqa::detail;
@@ -255,11 +256,7 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
     const int K = s->cfg.cycles_per_step;
     const int n = (int)s->active.size();
     constexpr int kVariants = kSweepVariants;
-    struct Entry {
-        double cost;
-        uint32_t code;
-    };
-    std::vector<Entry> lists[kVariants];
+    std::vector<WorkItem> lists[kVariants];
     int max_np[kVariants] = {}, max_delay[kVariants] = {};
     s->items.resize(n);
     double updates = 0;
@@ -281,11 +278,13 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
     }
     s->work.clear();
     size_t off[kVariants], len[kVariants];
+    const int xcds = device_xcd_count(s->cfg.device);
     for (int v = 0; v < kVariants; ++v) {
-        std::stable_sort(lists[v].begin(), lists[v].end(), [](const Entry& x, const Entry& y) { return x.cost > y.cost; });
+        std::stable_sort(lists[v].begin(), lists[v].end(), [](const WorkItem& x, const WorkItem& y) { return x.cost > y.cost; });
+        lists[v] = xcd_grouped(lists[v], xcds);
         off[v] = s->work.size();
         len[v] = lists[v].size();
-        for (const Entry& e : lists[v]) s->work.push_back(e.code);
+        for (const WorkItem& e : lists[v]) s->work.push_back(e.code);
     }
     const size_t need = (sizeof(SweepArgs) * n + 255) / 256 * 256 + sizeof(uint32_t) * s->work.size();
     if (need > s->table_bytes) {
