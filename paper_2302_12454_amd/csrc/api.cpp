@@ -122,36 +122,6 @@ int device_xcd_count(int device) {
     return v;
 }
 
-std::vector<WorkItem> xcd_grouped(const std::vector<WorkItem>& sorted, int xcds) {
-    if (xcds < 2 || sorted.empty()) return sorted;
-    std::vector<size_t> starts;   // first item of each anneal
-    for (size_t i = 0; i < sorted.size(); ++i)
-        if (i == 0 || (sorted[i].code >> 16) != (sorted[i - 1].code >> 16)) starts.push_back(i);
-    const size_t groups = starts.size();
-    const size_t g = sorted.size() / groups;
-    for (size_t k = 0; k < groups; ++k) {
-        const size_t end = k + 1 < groups ? starts[k + 1] : sorted.size();
-        if (end - starts[k] != g) return sorted;   // anneals of different item counts: keep the cost order
-    }
-    if (groups < (size_t)xcds) return sorted;
-    std::vector<std::vector<WorkItem>> q(xcds);
-    const size_t full = groups - groups % xcds;
-    for (size_t k = 0; k < full; ++k) {
-        const size_t round = k / xcds, pos = k % xcds;
-        const size_t x = (round % 2 == 0) ? pos : xcds - 1 - pos;
-        q[x].insert(q[x].end(), sorted.begin() + starts[k], sorted.begin() + starts[k] + g);
-    }
-    size_t j = 0;
-    for (size_t i = full * g; i < sorted.size(); ++i, ++j) q[j % xcds].push_back(sorted[i]);
-    // queue lengths are non-increasing in x and differ by at most one, so position k * xcds + x is q[x][k]
-    std::vector<WorkItem> out;
-    out.reserve(sorted.size());
-    for (size_t k = 0; out.size() < sorted.size(); ++k)
-        for (int x = 0; x < xcds; ++x)
-            if (k < q[x].size()) out.push_back(q[x][k]);
-    return out;
-}
-
 // Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
 // block, bit planes that fit in LDS, and at least 1024 padded rows (1536 for a plain anneal, `plain`).  With
 // fewer rows the K loop of a tile is short and two 64-column workgroups per CU hide its latency better than
