@@ -67,8 +67,10 @@ typedef struct ssqa_problem* ssqa_problem_t;
  *   out     : receives the handle.
  * J is stored as P signed int8 planes with J = sum_p 256^p J_p (P = 1 when every |J_ij| <= 127),
  * zero-padded to a multiple of 128 rows and columns, and additionally as fp4 (e2m1) when every J_ij is
- * one of 0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J_ij| is below 2^21 (then the fp4 field
- * product with fp32 accumulation is exact).
+ * one of 0, +-1, +-2, +-3, +-4, +-6 and B + 128 < 2^22, where B = max_i (|h_i| + 2 sum_j |J_ij|).  An
+ * anneal uses the fp4 copy only while B + n_rnd + (1 + mode) max_t |J_perp(t)| + 128 < 2^22: every
+ * partial sum of its fp32 accumulation is then an integer inside [2^23, 2^24), so the field product is
+ * exact (Eq. 6a-b need the field exactly).
  * Fails with SSQA_EINVAL for a bad size, pointer or non-symmetric J, and with SSQA_ERANGE when
  * 2 * sum_i |h_i| + sum_ij |J_ij| >= 2^30 (energies and fields must stay inside int32).
  */
@@ -79,8 +81,8 @@ ssqa_status ssqa_create_problem(int32_t n_spins, const int32_t* h, const int32_t
 void ssqa_destroy_problem(ssqa_problem_t problem);
 
 /* N, the number of int8 planes P, the padded size of the device layout, and 1 when the fp4 copy of
- * J exists (operand_format 2 is then available and is what operand_format 0 picks), else 0.  A NULL
- * handle gives 0. */
+ * J exists (operand_format 2 is then available to anneals whose noise and coupling keep the bound above,
+ * and is what operand_format 0 picks for them), else 0.  A NULL handle gives 0. */
 int32_t ssqa_problem_spins(ssqa_problem_t problem);
 int32_t ssqa_problem_planes(ssqa_problem_t problem);
 int32_t ssqa_problem_padded(ssqa_problem_t problem);
@@ -129,11 +131,11 @@ typedef struct ssqa_anneal_params {
                                   CU) and the planes fit in LDS), or
                                   32 / 64 / 128 (128 needs fp4 operands, else
                                   SSQA_ENOTSUP).  A tiling choice only: results do not depend on it */
-    int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when every J_ij is one of
-                                  0, +-1, +-2, +-3, +-4, +-6 and every row sum of |J| is below 2^21,
-                                  else int8 planes); 1 = int8 planes; 2 = fp4 (e2m1, fp32
-                                  accumulation, exact under the same conditions; SSQA_ENOTSUP
-                                  otherwise).  Results do not depend on it                         */
+    int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when the problem has an
+                                  fp4 copy and B + n_rnd + (1 + mode) max_t |J_perp(t)| + 128 < 2^22,
+                                  see ssqa_create_problem, else int8 planes); 1 = int8 planes; 2 = fp4
+                                  (e2m1, fp32 accumulation, exact under the same conditions;
+                                  SSQA_ENOTSUP otherwise).  Results do not depend on it            */
     int32_t start_cycle;       /* 0 for a fresh anneal; t0 in (0, cycles]: continue from the state
                                   `resume` holds after t0 cycles (best_energy and first_hit are then
                                   read as well as written: they must hold that run's values)      */

@@ -176,6 +176,12 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
     Checkpoint / resume: ``checkpoint=True`` returns the state after the last cycle run (``stop_cycle``,
     or all ``cycles``) in ``result.checkpoint``; ``resume=state`` continues from it (pass the interrupted
     run's ``out`` as well, since best energies and first hits carry over)."""
+    return _anneal_call("ssqa_anneal", **locals())
+
+
+def _anneal_call(fn: str, *, problem, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, seed,
+                 coupling_mode, target, trace, final_is, cycles_per_launch, block_columns, operand_format,
+                 stream, out, stop_cycle, resume, checkpoint) -> AnnealResult:
     import torch
     lib = _lib.load()
     if out is None:
@@ -198,8 +204,7 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
         p.start_cycle = int(resume.cycle)
         p.resume = ctypes.pointer(rs)
     o, ck = _outputs(out)
-    _check(lib.ssqa_anneal(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)),
-           "ssqa_anneal")
+    _check(getattr(lib, fn)(problem.handle, ctypes.byref(p), ctypes.byref(o), _stream_handle(stream)), fn)
     del keep, rs, ck
     return out
 

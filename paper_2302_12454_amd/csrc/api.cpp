@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,54 @@ void retain_pool_memory(int device) {
     done[device] = true;
 }
 
+// Pinned host staging for the host arrays (schedules) that asynchronous calls copy to the device.  The call
+// copies the caller's array into a slot and returns at once; a slot is reused only after the event recorded
+// behind its copy has completed.  Slots are kept per device until the process ends.
+namespace {
+struct StageSlot {
+    int device;
+    size_t bytes;
+    void* host;
+    hipEvent_t done;
+};
+std::mutex g_stage_mutex;
+std::vector<StageSlot> g_stage;
+}  // namespace
+
+hipError_t staged_upload(int device, void* dst, const void* const* srcs, const size_t* sizes, int count,
+                         hipStream_t stream) {
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) total += sizes[i];
+    if (total == 0) return hipSuccess;
+    std::lock_guard<std::mutex> lock(g_stage_mutex);
+    StageSlot* slot = nullptr;
+    for (StageSlot& s : g_stage)
+        if (s.device == device && s.bytes >= total && hipEventQuery(s.done) == hipSuccess) {
+            slot = &s;
+            break;
+        }
+    if (!slot) {
+        StageSlot s{device, std::max<size_t>(total, 64 * 1024), nullptr, nullptr};
+        hipError_t e = hipHostMalloc(&s.host, s.bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipHostFree(s.host);
+            return e;
+        }
+        g_stage.push_back(s);
+        slot = &g_stage.back();
+    }
+    char* h = static_cast<char*>(slot->host);
+    for (int i = 0; i < count; ++i) {
+        std::memcpy(h, srcs[i], sizes[i]);
+        h += sizes[i];
+    }
+    hipError_t e = hipMemcpyAsync(dst, slot->host, total, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(slot->done, stream);
+    return e;
+}
+
 int planes_needed(int32_t v) {
     int p = 0;
     do {
@@ -70,9 +119,22 @@ int planes_needed(int32_t v) {
     return p;
 }
 
+// Whether every fp32 partial sum of the fp4 field product stays exact for this anneal.  The accumulator of
+// row i starts at 1.5 * 2^23 plus v0 = h_i - sum_j J_ij + adj with |adj| <= n_rnd + (1 + mode) max_t |J_perp(t)|
+// + 128, and each MFMA adds 2 J_ij x_j for some of the j: every partial sum is 1.5 * 2^23 plus an integer of
+// magnitude at most |h_i| + 2 sum_j |J_ij| + |adj|.  While that stays below 2^22 the sum lies in [2^23, 2^24),
+// where fp32 represents every integer, so no rounding occurs in any summation order and the bits read back are
+// 0x4B400000 plus the integer (Eq. 6a-b need the field exactly).  Schedules must already be checked.
+bool fp4_fits(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    long long q_max = 0;
+    for (int t = 0; t < pa->cycles; ++t) q_max = std::max(q_max, std::llabs((long long)pa->jperp[t]));
+    const long long bound = prob->fp4_bound + pa->noise_amp + (1LL + pa->coupling_mode) * q_max + 128;
+    return bound < (1LL << 22);
+}
+
 bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
-    if (pa->operand_format == 1) return false;
-    return prob->dev.J4 != nullptr;
+    if (pa->operand_format == 1 || prob->dev.J4 == nullptr) return false;
+    return fp4_fits(prob, pa);
 }
 
 // The byte-parallel counter update applies when alpha = 1 and every counter plus 128 plus its noise and
@@ -92,10 +154,14 @@ bool fast_epilogue(const ssqa_anneal_params* pa) {
 
 // Columns per workgroup: the requested width, or 64 when R <= 64 and the bit planes fit in LDS, else 32
 // (plain_layout may widen an automatic 64 to 128).
-int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+int block_columns_for(int np, const ssqa_anneal_params* pa) {
     if (pa->block_columns == 32 || pa->block_columns == 64 || pa->block_columns == 128) return pa->block_columns;
-    if (pa->replicas <= 64 && sweep_lds_bytes(prob->dev.np, pa->delay, 64) <= 160 * 1024) return 64;
+    if (pa->replicas <= 64 && sweep_lds_bytes(np, pa->delay, 64) <= 160 * 1024) return 64;
     return 32;
+}
+
+int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    return block_columns_for(prob->dev.np, pa);
 }
 
 int device_cu_count(int device) {
@@ -158,13 +224,7 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
     if (R < 1 || T < 1 || SC < 0) return fail(SSQA_EINVAL, "replicas, trials must be >= 1 and cycles >= 0");
     if (pa->block_columns != 0 && pa->block_columns != 32 && pa->block_columns != 64 && pa->block_columns != 128)
         return fail(SSQA_EINVAL, "block_columns must be 0, 32, 64 or 128");
-    if (pa->block_columns == 128 && !use_fp4(prob, pa))
-        return fail(SSQA_ENOTSUP, "128 columns per workgroup need fp4 operands");
     if (pa->operand_format < 0 || pa->operand_format > 2) return fail(SSQA_EINVAL, "operand_format must be 0, 1 or 2");
-    if (pa->operand_format == 2 && !prob->dev.J4)
-        return fail(SSQA_ENOTSUP, "fp4 operands requested but J has entries outside {0, +-1, +-2, +-3, +-4, +-6}");
-    const int nb = block_columns(prob, pa);
-    if (R > nb) return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d columns per workgroup", R, nb);
     if ((long long)T * R > (1LL << 28)) return fail(SSQA_EINVAL, "trials * replicas too large");
     if (pa->delay < 0 || pa->delay > kMaxDelay) return fail(SSQA_EINVAL, "delay %d outside [0, %d]", pa->delay, kMaxDelay);
     if (pa->alpha < 1) return fail(SSQA_EINVAL, "alpha must be >= 1");
@@ -179,6 +239,17 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
         if (pa->jperp[t] < -(1 << 20) || pa->jperp[t] > (1 << 20))
             return fail(SSQA_EINVAL, "jperp[%d] = %d outside [-2^20, 2^20]", t, pa->jperp[t]);
     }
+    // operand format (the schedules are valid from here on)
+    if (pa->operand_format == 2 && !prob->dev.J4)
+        return fail(SSQA_ENOTSUP, "fp4 operands requested but J has entries outside {0, +-1, +-2, +-3, +-4, +-6} "
+                                  "or max_i(|h_i| + 2 sum_j |J_ij|) + 128 >= 2^22");
+    if (pa->operand_format == 2 && !fp4_fits(prob, pa))
+        return fail(SSQA_ENOTSUP, "fp4 operands requested but max_i(|h_i| + 2 sum_j |J_ij|) + n_rnd + "
+                                  "(1 + mode) max|jperp| + 128 >= 2^22: fp32 accumulation would not be exact");
+    if (pa->block_columns == 128 && !use_fp4(prob, pa))
+        return fail(SSQA_ENOTSUP, "128 columns per workgroup need fp4 operands");
+    const int nb = block_columns(prob, pa);
+    if (R > nb) return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d columns per workgroup", R, nb);
     if (sweep_lds_bytes(prob->dev.np, pa->delay, nb) > 160 * 1024)
         return fail(SSQA_ENOTSUP, "N = %d with delay %d needs %zu bytes of LDS per workgroup (> 160 KiB)",
                     prob->dev.n, pa->delay, sweep_lds_bytes(prob->dev.np, pa->delay, nb));
@@ -213,6 +284,105 @@ SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, cons
     a.first_hit = out->first_hit;
     a.trace = out->energy_trace;
     return a;
+}
+
+// Sizes of the device state of a plain anneal (counters, bit-plane history, schedules) in its layout.
+AnnealSizes anneal_sizes(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    const PlainLayout lay = plain_layout(prob, pa);
+    const int np = prob->dev.np;
+    AnnealSizes z;
+    z.layout = lay;
+    z.is_bytes = (size_t)lay.n_wg * lay.nb * np;
+    z.hist_bytes = (size_t)lay.n_wg * std::max(pa->delay, 1) * lay.nb * (np / 32) * 4;
+    z.sched_bytes = 2 * (size_t)std::max(pa->cycles, 1) * 4;
+    return z;
+}
+
+ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
+                        hipStream_t stream, const AnnealWorkspace* ws) {
+    if (!prob || !pa || !out) return fail(SSQA_EINVAL, "NULL problem, params or outputs");
+    const ssqa_status st = check_params(prob, pa, out);
+    if (st != SSQA_OK) return st;
+    const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
+    const int t0 = pa->start_cycle;
+    const int t1 = pa->stop_cycle == 0 ? SC : pa->stop_cycle;
+    if (t0 < 0 || t0 > SC) return fail(SSQA_EINVAL, "start_cycle = %d outside [0, cycles = %d]", t0, SC);
+    if (t1 < t0 || t1 > SC || (t1 == t0 && t1 != SC))
+        return fail(SSQA_EINVAL, "stop_cycle = %d must lie in (start_cycle, cycles] (or be 0)", pa->stop_cycle);
+    if (t0 > 0 && (!pa->resume || !pa->resume->counters || (pa->delay > 0 && !pa->resume->history)))
+        return fail(SSQA_EINVAL, "start_cycle > 0 needs a resume state with counters (and history when d > 0)");
+    const ssqa_anneal_state* ckpt = out->checkpoint;
+    if (ckpt && (!ckpt->counters || (pa->delay > 0 && !ckpt->history)))
+        return fail(SSQA_EINVAL, "checkpoint needs counters (and history when d > 0)");
+
+    DeviceGuard guard(prob->device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
+    const AnnealSizes z = anneal_sizes(prob, pa);
+    const int nb = z.layout.nb, tpw = z.layout.tpw, n_wg = z.layout.n_wg;
+    const int np = prob->dev.np;
+
+    int8_t* is_state = nullptr;
+    uint32_t* hist = nullptr;
+    int32_t* d_sched = nullptr;
+    hipError_t e = hipSuccess;
+    if (ws) {
+        is_state = ws->is_state;
+        hist = ws->hist;
+        d_sched = ws->sched;
+        // The caller's schedules go straight to the workspace; the host waits for the copy, so that no
+        // staging memory is needed and the caller may free its arrays on return.
+        if (SC > 0) e = hipMemcpyAsync(d_sched, pa->jperp, (size_t)SC * 4, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && SC > 0)
+            e = hipMemcpyAsync(d_sched + SC, pa->i0, (size_t)SC * 4, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    } else {
+        retain_pool_memory(prob->device);
+        e = hipMallocAsync(reinterpret_cast<void**>(&is_state), z.is_bytes, stream);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&hist), z.hist_bytes, stream);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&d_sched), z.sched_bytes, stream);
+        if (e == hipSuccess && SC > 0) {
+            // copied through pinned staging: the call returns without waiting for the device
+            const void* srcs[2] = {pa->jperp, pa->i0};
+            const size_t sizes[2] = {(size_t)SC * 4, (size_t)SC * 4};
+            e = staged_upload(prob->device, d_sched, srcs, sizes, 2, stream);
+        }
+    }
+    // [jperp | i0], SC entries each (one unused word each when SC = 0)
+    const int32_t* d_jperp = d_sched;
+    const int32_t* d_i0 = d_sched + std::max(SC, 1);
+
+    if (e == hipSuccess && t0 > 0)
+        e = launch_import_state(pa->resume->counters, pa->resume->history, prob->dev.n, np, R, T, tpw, nb, pa->delay,
+                                is_state, hist, stream);
+    if (e == hipSuccess) {
+        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist, nb, tpw);
+        const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(t1 - t0, 1);
+        int t = t0;
+        do {
+            a.t_begin = t;
+            a.t_end = std::min(t1, t + chunk);
+            a.final_pass = (a.t_end == SC) ? 1 : 0;
+            a.save_hist = (!a.final_pass || ckpt) ? 1 : 0;
+            e = launch_sweep(a, n_wg, stream);
+            t = a.t_end;
+        } while (e == hipSuccess && t < t1);
+        if (e == hipSuccess && out->final_is)
+            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, out->final_is, stream);
+        if (e == hipSuccess && ckpt) {
+            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, ckpt->counters, stream);
+            if (e == hipSuccess && pa->delay > 0)
+                e = launch_export_history(hist, prob->dev.n, np, R, T, tpw, nb, pa->delay, ckpt->history, stream);
+        }
+    }
+    if (!ws) {
+        if (is_state) (void)hipFreeAsync(is_state, stream);
+        if (hist) (void)hipFreeAsync(hist, stream);
+        if (d_sched) (void)hipFreeAsync(d_sched, stream);
+    }
+    if (e != hipSuccess) {
+        return e == hipErrorOutOfMemory ? fail(SSQA_ENOMEM, "device allocation failed") : hip_fail(e, "anneal");
+    }
+    return SSQA_OK;
 }
 
 }  // namespace detail
@@ -254,7 +424,8 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     if (!h || !J) return fail(SSQA_EINVAL, "h or J is NULL");
     long long total = 0;
     int planes = 1;
-    bool fp4_exact = true;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6} and every row sum of |J| < 2^21
+    bool fp4_codes = true;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6}
+    long long fp4_bound = 0;      // max_i (|h_i| + 2 sum_j |J_ij|), see fp4_fits
     for (int i = 0; i < n; ++i) {
         total += 2LL * std::llabs((long long)h[i]);
         long long row_abs = 0;
@@ -267,11 +438,14 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
             row_abs += std::llabs((long long)v);
             planes = std::max(planes, planes_needed(v));
             const int m = v < 0 ? -v : v;
-            if (m > 6 || m == 5) fp4_exact = false;
+            if (m > 6 || m == 5) fp4_codes = false;
         }
-        if (row_abs >= (1LL << 21)) fp4_exact = false;
+        fp4_bound = std::max(fp4_bound, std::llabs((long long)h[i]) + 2 * row_abs);
         if (total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
     }
+    // The fp4 copy is built when J is representable and at least an anneal without noise and coupling keeps
+    // the fp32 accumulation exact; each anneal checks its own bound (fp4_fits).
+    const bool fp4_exact = fp4_codes && fp4_bound + 128 < (1LL << 22);
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
         return fail(SSQA_EDEVICE, "no HIP device available");
@@ -283,6 +457,7 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     ssqa_problem* p = new (std::nothrow) ssqa_problem();
     if (!p) return fail(SSQA_ENOMEM, "host allocation failed");
     p->device = device;
+    p->fp4_bound = fp4_bound;
     int32_t* J32 = nullptr;
     int32_t* h32 = nullptr;
     const size_t plane_bytes = (size_t)planes * np * np;
@@ -334,75 +509,7 @@ int32_t ssqa_problem_fp4_exact(ssqa_problem_t p) { return p && p->J_fp4 ? 1 : 0;
 ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
                         void* hip_stream) {
     g_last_error.clear();
-    if (!prob || !pa || !out) return fail(SSQA_EINVAL, "NULL problem, params or outputs");
-    const ssqa_status st = check_params(prob, pa, out);
-    if (st != SSQA_OK) return st;
-    const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
-    const int t0 = pa->start_cycle;
-    const int t1 = pa->stop_cycle == 0 ? SC : pa->stop_cycle;
-    if (t0 < 0 || t0 > SC) return fail(SSQA_EINVAL, "start_cycle = %d outside [0, cycles = %d]", t0, SC);
-    if (t1 < t0 || t1 > SC || (t1 == t0 && t1 != SC))
-        return fail(SSQA_EINVAL, "stop_cycle = %d must lie in (start_cycle, cycles] (or be 0)", pa->stop_cycle);
-    if (t0 > 0 && (!pa->resume || !pa->resume->counters || (pa->delay > 0 && !pa->resume->history)))
-        return fail(SSQA_EINVAL, "start_cycle > 0 needs a resume state with counters (and history when d > 0)");
-    const ssqa_anneal_state* ckpt = out->checkpoint;
-    if (ckpt && (!ckpt->counters || (pa->delay > 0 && !ckpt->history)))
-        return fail(SSQA_EINVAL, "checkpoint needs counters (and history when d > 0)");
-
-    DeviceGuard guard(prob->device);
-    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
-    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    retain_pool_memory(prob->device);
-    const PlainLayout lay = plain_layout(prob, pa);
-    const int nb = lay.nb, tpw = lay.tpw, n_wg = lay.n_wg;
-    const int np = prob->dev.np;
-    const size_t is_bytes = (size_t)n_wg * nb * np;
-    const size_t hist_bytes = (size_t)n_wg * std::max(pa->delay, 1) * nb * (np / 32) * 4;
-    const size_t sched_bytes = (size_t)std::max(SC, 1) * 4;
-
-    int8_t* is_state = nullptr;
-    uint32_t* hist = nullptr;
-    int32_t* d_jperp = nullptr;
-    int32_t* d_i0 = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&is_state), is_bytes, stream);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&hist), hist_bytes, stream);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&d_jperp), sched_bytes, stream);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&d_i0), sched_bytes, stream);
-    if (e == hipSuccess && SC > 0) e = hipMemcpyAsync(d_jperp, pa->jperp, (size_t)SC * 4, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && SC > 0) e = hipMemcpyAsync(d_i0, pa->i0, (size_t)SC * 4, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host schedules may be freed on return
-
-    if (e == hipSuccess && t0 > 0)
-        e = launch_import_state(pa->resume->counters, pa->resume->history, prob->dev.n, np, R, T, tpw, nb, pa->delay,
-                                is_state, hist, stream);
-    if (e == hipSuccess) {
-        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist, nb, tpw);
-        const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(t1 - t0, 1);
-        int t = t0;
-        do {
-            a.t_begin = t;
-            a.t_end = std::min(t1, t + chunk);
-            a.final_pass = (a.t_end == SC) ? 1 : 0;
-            a.save_hist = (!a.final_pass || ckpt) ? 1 : 0;
-            e = launch_sweep(a, n_wg, stream);
-            t = a.t_end;
-        } while (e == hipSuccess && t < t1);
-        if (e == hipSuccess && out->final_is)
-            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, out->final_is, stream);
-        if (e == hipSuccess && ckpt) {
-            e = launch_copy_final_is(is_state, np, prob->dev.n, R, T, tpw, nb, ckpt->counters, stream);
-            if (e == hipSuccess && pa->delay > 0)
-                e = launch_export_history(hist, prob->dev.n, np, R, T, tpw, nb, pa->delay, ckpt->history, stream);
-        }
-    }
-    if (is_state) (void)hipFreeAsync(is_state, stream);
-    if (hist) (void)hipFreeAsync(hist, stream);
-    if (d_jperp) (void)hipFreeAsync(d_jperp, stream);
-    if (d_i0) (void)hipFreeAsync(d_i0, stream);
-    if (e != hipSuccess) {
-        return e == hipErrorOutOfMemory ? fail(SSQA_ENOMEM, "device allocation failed") : hip_fail(e, "anneal");
-    }
-    return SSQA_OK;
+    return anneal_impl(prob, pa, out, reinterpret_cast<hipStream_t>(hip_stream), nullptr);
 }
 
 ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
@@ -603,8 +710,11 @@ ssqa_status ssqa_sa_anneal(ssqa_problem_t prob, const ssqa_sa_params* pa, const 
     retain_pool_memory(prob->device);
     double* d_beta = nullptr;
     hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&d_beta), sizeof(double) * std::max(pa->cycles, 1), stream);
-    if (e == hipSuccess && pa->cycles > 0)
-        e = hipMemcpyAsync(d_beta, pa->beta, sizeof(double) * pa->cycles, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && pa->cycles > 0) {
+        const void* src = pa->beta;
+        const size_t bytes = sizeof(double) * pa->cycles;
+        e = staged_upload(prob->device, d_beta, &src, &bytes, 1, stream);
+    }
     if (e == hipSuccess) {
         SAArgs a{};
         a.prob = prob->dev;

@@ -167,6 +167,7 @@ struct ssqa_problem {
     int8_t* J_planes;
     uint8_t* J_fp4;    // fp4 copy of J, or nullptr
     int32_t* rowvec;   // [h | h - rowsum | 2h - rowsum], np each
+    int64_t fp4_bound; // max_i (|h_i| + 2 sum_j |J_ij|): bounds the fp4 accumulator's partial sums
 };
 
 namespace ssqa {
@@ -185,10 +186,14 @@ struct DeviceGuard {
     ~DeviceGuard();
 };
 
+// Whether the fp4 field product of an anneal of `prob` with `pa` is exact (schedules already checked).
+bool fp4_fits(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Whether an anneal of `prob` with `pa` runs its field product on the fp4 copy of J.
 bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Columns per workgroup for an anneal of `prob` with `pa`: the requested 32, 64 or 128, else 64 or 32.
 int block_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// The same from the padded size alone (no problem needed).
+int block_columns_for(int np, const ssqa_anneal_params* pa);
 // Full argument check of one anneal; records the reason on failure.
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out);
 // Kernel arguments of one anneal (t_begin / t_end / final_pass left for the caller).  nb and tpw
@@ -201,6 +206,27 @@ struct PlainLayout {
     int nb, tpw, n_wg;
 };
 PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// Device state of one plain anneal: counters, bit-plane history and the two schedules ([jperp | i0]).
+struct AnnealSizes {
+    PlainLayout layout;
+    size_t is_bytes, hist_bytes, sched_bytes;
+};
+AnnealSizes anneal_sizes(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// Caller-provided device state of a plain anneal (at least the sizes anneal_sizes gives).
+struct AnnealWorkspace {
+    int8_t* is_state;
+    uint32_t* hist;
+    int32_t* sched;
+};
+// ssqa_anneal: with ws == nullptr the state is taken from the stream-ordered pool and the schedules are copied
+// through pinned staging (no host wait); with a workspace nothing is allocated and the host waits for the
+// schedule copy.  Checks the parameters first (anneal_sizes needs them valid).
+ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
+                        hipStream_t stream, const AnnealWorkspace* ws);
+// Copies `count` host arrays back to back to device memory `dst` on `stream` through pinned staging owned by
+// the library; returns without waiting for the copy.
+hipError_t staged_upload(int device, void* dst, const void* const* srcs, const size_t* sizes, int count,
+                         hipStream_t stream);
 int device_cu_count(int device);
 // Keep freed stream-ordered allocations in the device pool.
 void retain_pool_memory(int device);

@@ -53,13 +53,23 @@ struct Request {
     double submit_s = 0, admit_s = -1, done_s = -1;
 };
 
+int padded_rows(int n) { return (n + kTileRows - 1) / kTileRows * kTileRows; }
+
+// Workgroups of a request: whole trials per block of the width admission takes (block_columns_for), at least
+// one trial per block (a request whose replicas exceed the width is refused at admission).
+int64_t request_blocks(int n, const ssqa_anneal_params& pa) {
+    const int nb = block_columns_for(padded_rows(n), &pa);
+    const int64_t tpw = std::max(1, nb / pa.replicas);
+    return (pa.trials + tpw - 1) / tpw;
+}
+
 // Device bytes of one admitted request: int8 planes, the fp4 copy of J (counted whether or not the
 // problem turns out to be fp4-exact), row vectors, counters, bit-plane history, outputs, schedules.
-int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa, int nb) {
-    const int64_t np = (n + kTileRows - 1) / kTileRows * kTileRows;
+int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa) {
+    const int64_t np = padded_rows(n);
     const int64_t kp4 = fp4_k_extent((int)np);
-    const int64_t tpw = nb / pa.replicas;
-    const int64_t n_wg = (pa.trials + tpw - 1) / tpw;
+    const int64_t nb = block_columns_for((int)np, &pa);
+    const int64_t n_wg = request_blocks(n, pa);
     return planes_hint * np * np + np * kp4 / 2 + 12 * np + n_wg * nb * np +
            n_wg * std::max(pa.delay, 1) * nb * np / 8 + 12LL * pa.trials + 8LL * std::max(pa.cycles, 1) + 1024;
 }
@@ -103,8 +113,9 @@ ssqa_status admit(ssqa_server* s, Request* r) {
     st = check_params(r->prob, &pa, &probe);
     if (st != SSQA_OK) return st;
     r->nb = block_columns(r->prob, &pa);
-    const int tpw = r->nb / pa.replicas;
+    const int tpw = r->nb / pa.replicas;   // >= 1: check_params refused R > nb
     r->n_wg = (pa.trials + tpw - 1) / tpw;
+    if (r->n_wg > 65535) return fail(SSQA_EINVAL, "request needs %d workgroups (> 65535)", r->n_wg);
     const int np = r->prob->dev.np;
     const int SC = std::max(pa.cycles, 1);
     const size_t o_sched = 0;
@@ -171,6 +182,15 @@ ssqa_status ssqa_server_submit(ssqa_server_t s, const ssqa_request* req, int64_t
     if (pa.start_cycle != 0 || (pa.stop_cycle != 0 && pa.stop_cycle != pa.cycles))
         return fail(SSQA_EINVAL, "start_cycle and stop_cycle must be 0 for served requests");
     if (req->early_exit != 0 && req->early_exit != 1) return fail(SSQA_EINVAL, "early_exit must be 0 or 1");
+    if (pa.replicas > 64) return fail(SSQA_ENOTSUP, "replicas = %d: served requests take at most 64", pa.replicas);
+    if (pa.block_columns != 0 && pa.block_columns != 32 && pa.block_columns != 64 && pa.block_columns != 128)
+        return fail(SSQA_EINVAL, "block_columns must be 0, 32, 64 or 128");
+    if ((long long)pa.trials * pa.replicas > (1LL << 28)) return fail(SSQA_EINVAL, "trials * replicas too large");
+    // A launch's work code keeps the block index in 16 bits.
+    const int64_t blocks = request_blocks(req->n_spins, pa);
+    if (blocks > 65535)
+        return fail(SSQA_EINVAL, "request needs %lld workgroups of whole trials (> 65535): fewer trials per request",
+                    (long long)blocks);
     auto r = std::make_unique<Request>();
     r->id = s->next_id++;
     r->n = req->n_spins;
@@ -213,7 +233,7 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
             s->queue.pop_front();
             continue;
         }
-        const int64_t need = request_bytes(r->n, r->planes, r->params, 32);
+        const int64_t need = request_bytes(r->n, r->planes, r->params);
         if (need > s->cfg.memory_budget) {          // can never fit: refuse it
             s->queue.pop_front();
             r->state = SSQA_REQ_FAILED;

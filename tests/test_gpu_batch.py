@@ -176,7 +176,8 @@ def test_batch_widens_blocks_from_1024_rows(lib):
 
 def test_uneven_gi_batch(lib):
     """Forty GI instances of uneven size (n from 10 to 50, edge probability 0.3-0.7), R = 32, T = 64, in
-    one launch: every instance equals its separate anneal; two instances replayed by the oracle."""
+    one launch: every instance equals its separate anneal; the two smallest instances are replayed by the
+    oracle on two trials, and the largest on two trials with its energy trace and final counters."""
     import torch
     _note("case uneven GI batch of 40")
     pairs = uneven_gi_batch(40, seed_base=1000)
@@ -189,6 +190,8 @@ def test_uneven_gi_batch(lib):
         jobs.append((prob, dict(replicas=32, trials=64, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=noise,
                                 delay=1, seed=g, target=e_star)))
         models.append((h, J, e_star))
+    largest = max(range(len(pairs)), key=lambda g: pairs[g].n)
+    jobs[largest][1].update(trace=True, final_is=True)
     batch = lib.Batch(jobs)
     res = [_host(r) for r in batch.run()]
     torch.cuda.synchronize()
@@ -205,4 +208,9 @@ def test_uneven_gi_batch(lib):
         assert np.array_equal(res[g]["best"][[0, 63]], ref.best)
         assert np.array_equal(res[g]["first_hit"][[0, 63]], ref.first_hit)
         assert (res[g]["best"] >= e_star).all()
+    h, J, e_star = models[largest]
+    _note(f"case uneven GI batch: oracle replay of the largest instance, N = {len(h)}")
+    ref = run_oracle(h, J, replicas=32, trials=[0, 63], cycles=SC, q=q, i0=i0, alpha=1, noise=noise, delay=1,
+                     seed=largest, target=e_star)
+    assert_same(res[largest], ref, trial_idx=[0, 63])
     batch.close()

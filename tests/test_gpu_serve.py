@@ -141,3 +141,55 @@ def test_cancel(lib):
     assert s.poll(keep)["state"] == "done" and s.poll(keep)["cycles_done"] == 400
     assert s.stats()["memory_in_use"] == 0
     s.close()
+
+
+def test_r64_request_equals_anneal(lib):
+    """A request with R = 64 replicas (one trial per 64-column block) is admitted, charged and run like any
+    other, alone and beside an R = 32 request, and equals ssqa_anneal."""
+    import torch
+    _note("case serve R=64")
+    h, J, kw = _request(lib, 8, 50, SC=120, R=64, T=5)
+    s = lib.Server(cycles_per_step=40)
+    other = s.submit(*_request(lib, 7, 51, SC=80)[:2], **_request(lib, 7, 51, SC=80)[2])
+    r = s.submit(h, J, **kw)
+    _drain(s, [other, r])
+    x = s.poll(r)
+    assert x["state"] == "done" and x["cycles_done"] == 120 and x["memory_bytes"] > 0
+    ref = lib.ssqa_anneal(lib.Problem(h, J), **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(x["best"], ref.best_energy.cpu().numpy())
+    assert np.array_equal(x["first_hit"], ref.first_hit.cpu().numpy())
+    s.close()
+
+
+def test_large_request_in_a_mix(lib):
+    """An N = 10^4 GI request (n = 100; J of 100 MB as int32) served beside two small ones gives, trial for
+    trial, the best energy and first hit of ssqa_anneal; trial 5 is replayed by the oracle over all cycles."""
+    import torch
+    from oracle import gi, ssqa
+    from tests.parity_util import paper_schedules as sched
+    _note("case serve N=10^4 in a mix")
+    SC, R, T = 40, 32, 16
+    pair = random_gi_pair(100, 0.5, 5003)
+    h, J, e_star = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, 12)
+    q, i0, noise = sched(SC, tau=10)
+    kw = dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=noise, delay=1, seed=77,
+              target=e_star)
+    s = lib.Server(cycles_per_step=15)
+    small = [s.submit(*_request(lib, n, 60 + n, SC=60)[:2], **_request(lib, n, 60 + n, SC=60)[2]) for n in (6, 12)]
+    big = s.submit(h, J, **kw)
+    _drain(s, small + [big])
+    x = s.poll(big)
+    assert x["state"] == "done" and x["cycles_done"] == SC
+    prob = lib.Problem(h, J)
+    ref = lib.ssqa_anneal(prob, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(x["best"], ref.best_energy.cpu().numpy())
+    assert np.array_equal(x["first_hit"], ref.first_hit.cpu().numpy())
+    prob.close()
+    del ref
+    ho, Jo, eo = gi.gi_ising(pair.a1, pair.a2, 12)
+    assert eo == e_star
+    orc = ssqa.anneal(ho, Jo, R, [5], SC, q, i0, 1, noise, 1, seed=77, target=e_star)
+    assert x["best"][5] == orc.best[0] and x["first_hit"][5] == orc.first_hit[0]
+    s.close()

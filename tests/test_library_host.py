@@ -204,3 +204,45 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def _submit(lib, n, R, T, SC=10):
+    """ssqa_server_submit of a small random model with R replicas and T trials (host only, no device work)."""
+    h = (ctypes.c_int32 * n)(*([1] * n))
+    J = (ctypes.c_int32 * (n * n))()
+    q = (ctypes.c_int32 * SC)(*([0] * SC))
+    i0 = (ctypes.c_int32 * SC)(*([24] * SC))
+    req = lib_mod.Request()
+    req.n_spins = n
+    req.h = ctypes.cast(h, lib_mod.c_int32_p)
+    req.J = ctypes.cast(J, lib_mod.c_int32_p)
+    p = req.params
+    p.replicas, p.trials, p.cycles, p.delay, p.alpha, p.noise_amp = R, T, SC, 1, 1, 12
+    p.jperp = ctypes.cast(q, lib_mod.c_int32_p)
+    p.i0 = ctypes.cast(i0, lib_mod.c_int32_p)
+    cfg = lib_mod.ServerConfig(0, 10, 16, 1 << 30)
+    server = ctypes.c_void_p()
+    assert lib.ssqa_server_create(ctypes.byref(cfg), ctypes.byref(server)) == 0
+    rid = ctypes.c_int64()
+    st = lib.ssqa_server_submit(server, ctypes.byref(req), ctypes.byref(rid))
+    msg = lib.ssqa_last_error().decode()
+    lib.ssqa_server_destroy(server)
+    return st, msg
+
+
+def test_server_submit_bounds_requests(lib):
+    """Submit refuses, before any device work, a request whose blocks of whole trials would not fit the 16-bit
+    block index of a launch's work code (R = 64: one trial per block, T = 70,000 -> SSQA_EINVAL) and one with
+    more than 64 replicas (SSQA_ENOTSUP); R = 33 and R = 64 within range are accepted (the memory charge
+    then takes one trial per block instead of dividing by zero)."""
+    st, msg = _submit(lib, 4, 64, 70_000)
+    assert st == -1 and "65535" in msg, msg
+    st, msg = _submit(lib, 4, 65, 4)
+    assert st == -5 and "64" in msg, msg
+    for R in (33, 64):
+        st, msg = _submit(lib, 4, R, 65_535)
+        assert st == 0, msg
+    st, msg = _submit(lib, 4, 1, 65_535 * 64)
+    assert st == 0, msg
+    st, msg = _submit(lib, 4, 1, 65_535 * 64 + 1)
+    assert st == -1, msg
