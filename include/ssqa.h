@@ -170,6 +170,24 @@ typedef struct ssqa_anneal_outputs {
 ssqa_status ssqa_anneal(ssqa_problem_t problem, const ssqa_anneal_params* params,
                         const ssqa_anneal_outputs* outputs, void* hip_stream);
 
+/*
+ * ssqa_anneal for callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, checks and results, bit for bit, but the anneal's device state (counters,
+ * bit-plane history and schedules, in the layout ssqa_anneal would choose) lives in a fixed 64 MiB array
+ * that the library holds on each device it runs this call on until the process ends.  Nothing is allocated:
+ * no hipMalloc, no stream-ordered pool, no pinned staging.  The caller still passes the problem and the
+ * output buffers.
+ *   - An anneal whose state exceeds 64 MiB (about T * R * N bytes of counters, plus 1/8 of that per unit
+ *     of delay d, plus 8 * SC bytes of schedules) fails with SSQA_ENOTSUP before any device work.
+ *   - The host waits for the copy of the schedules into the array before returning (so the caller may
+ *     free them); the anneal itself runs asynchronously on `hip_stream`.
+ *   - Every call on a device shares that device's array and leaves its contents behind (nothing in it has
+ *     to start at zero).  Calls on one stream are ordered; calls that overlap on one device (several
+ *     streams or host threads) race on the array and must be serialised by the caller.
+ */
+ssqa_status ssqa_anneal_noalloc(ssqa_problem_t problem, const ssqa_anneal_params* params,
+                                const ssqa_anneal_outputs* outputs, void* hip_stream);
+
 /* ------------------------------------------------------------------------------------------- */
 /* Batched form: many anneals of uneven size in one persistent launch, replayed from a HIP graph.*/
 /* ------------------------------------------------------------------------------------------- */

@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     Server,
     SSQAError,
     ssqa_anneal,
+    ssqa_anneal_noalloc,
     ssqa_batch_create,
     ssqa_create_problem,
     ssqa_energy,

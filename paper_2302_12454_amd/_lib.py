@@ -128,6 +128,8 @@ SIGNATURES = {
     "ssqa_problem_fp4_exact": (ctypes.c_int32, [ctypes.c_void_p]),
     "ssqa_anneal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams),
                                    ctypes.POINTER(AnnealOutputs), ctypes.c_void_p]),
+    "ssqa_anneal_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams),
+                                           ctypes.POINTER(AnnealOutputs), ctypes.c_void_p]),
     "ssqa_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p]),
     "ssqa_qmc_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,

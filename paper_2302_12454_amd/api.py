@@ -179,6 +179,18 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
     return _anneal_call("ssqa_anneal", **locals())
 
 
+def ssqa_anneal_noalloc(problem: Problem, *, replicas: int, trials: int, cycles: int, jperp, i0, alpha: int,
+                        noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
+                        trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0,
+                        block_columns: int = 0, operand_format: int = 0, stream=None,
+                        out: AnnealResult | None = None, stop_cycle: int = 0, resume: "AnnealState | None" = None,
+                        checkpoint: bool = False) -> AnnealResult:
+    """ssqa_anneal_noalloc: ssqa_anneal with the anneal's device state in the library's fixed per-device
+    scratch (no device allocation by the library).  Same arguments and results as ``ssqa_anneal``; the
+    outputs are still torch tensors unless ``out`` brings them."""
+    return _anneal_call("ssqa_anneal_noalloc", **locals())
+
+
 def _anneal_call(fn: str, *, problem, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, seed,
                  coupling_mode, target, trace, final_is, cycles_per_launch, block_columns, operand_format,
                  stream, out, stop_cycle, resume, checkpoint) -> AnnealResult:

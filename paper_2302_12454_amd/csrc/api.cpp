@@ -512,6 +512,31 @@ ssqa_status ssqa_anneal(ssqa_problem_t prob, const ssqa_anneal_params* pa, const
     return anneal_impl(prob, pa, out, reinterpret_cast<hipStream_t>(hip_stream), nullptr);
 }
 
+ssqa_status ssqa_anneal_noalloc(ssqa_problem_t prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
+                                void* hip_stream) {
+    g_last_error.clear();
+    if (!prob || !pa || !out) return fail(SSQA_EINVAL, "NULL problem, params or outputs");
+    const ssqa_status st = check_params(prob, pa, out);   // anneal_sizes needs valid parameters
+    if (st != SSQA_OK) return st;
+    const AnnealSizes z = anneal_sizes(prob, pa);
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t o_hist = align(z.is_bytes);
+    const size_t o_sched = o_hist + align(z.hist_bytes);
+    const size_t need = o_sched + align(z.sched_bytes);
+    if (need > kFixedScratchBytes)
+        return fail(SSQA_ENOTSUP, "anneal needs %zu bytes of device state; the fixed scratch of ssqa_anneal_noalloc "
+                                  "holds %zu (use ssqa_anneal)", need, kFixedScratchBytes);
+    DeviceGuard guard(prob->device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice failed");
+    void* base = nullptr;
+    const hipError_t e = fixed_scratch(prob->device, &base);
+    if (e != hipSuccess) return hip_fail(e, "address of the fixed scratch");
+    char* p = static_cast<char*>(base);
+    const AnnealWorkspace ws{reinterpret_cast<int8_t*>(p), reinterpret_cast<uint32_t*>(p + o_hist),
+                             reinterpret_cast<int32_t*>(p + o_sched)};
+    return anneal_impl(prob, pa, out, reinterpret_cast<hipStream_t>(hip_stream), &ws);
+}
+
 ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
                               const ssqa_anneal_outputs* outputs, ssqa_batch_t* out) {
     g_last_error.clear();

@@ -126,6 +126,12 @@ hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t
                          hipStream_t stream);
 hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, int32_t trials, int32_t R,
                              int32_t jperp, int64_t* out, hipStream_t stream);
+// Fixed device scratch of ssqa_anneal_noalloc (sweep.hip): kFixedScratchBytes on every device the library
+// runs it on, held until the process ends.
+constexpr size_t kFixedScratchBytes = size_t(64) << 20;
+// Device address of the current device's copy of that scratch (`device` must be current).  Looked up once per
+// device and kept.
+hipError_t fixed_scratch(int device, void** ptr);
 
 
 // Arguments of the simulated-annealing baseline kernel (sa.hip): one wave per chain.

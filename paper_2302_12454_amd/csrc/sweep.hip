@@ -23,6 +23,7 @@
 //  * J with entries beyond int8 is split into P planes; the K loop runs once per plane, most
 //    significant first, scaling the accumulator by 256 in between (exact Horner evaluation).
 
+#include <mutex>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -1145,6 +1146,28 @@ hipError_t launch_copy_final_is(const int8_t* is_state, int32_t np, int32_t n, i
                                 int32_t nb, int8_t* out, hipStream_t stream) {
     hipLaunchKernelGGL(copy_final_is_kernel, dim3(T * R), dim3(256), 0, stream, is_state, np, n, R, T, tpw, nb, out);
     return hipGetLastError();
+}
+
+// Device state (counters, bit-plane history, schedules) of ssqa_anneal_noalloc, for callers that cannot
+// allocate: a fixed array in the code object, one copy per device.  Host code never passes its name to a
+// kernel (on the host the name is only a stand-in); it looks the device address up once per device with
+// that device current and passes that address instead.
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+
+hipError_t fixed_scratch(int device, void** ptr) {
+    static std::mutex lock;
+    static void* addr[64] = {};
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_energy(const DeviceProblem& prob, const int8_t* spins, int32_t cols, int64_t* energies,
