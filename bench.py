@@ -5,9 +5,10 @@ trials, plus the final energy pass), through the C ABI, with the problem already
 resident on the GPU.  Default workload: GI with n = 50 (N = 2500 spins), G(50, 0.5)
 plus a relabelled copy (graph seed 2), R = 64 replicas, T = 1024 trials, SC = 2000
 cycles, the paper's SSQA schedule (Table 2, tau = 100) at integer scale 12.  The
-default line also carries the oracle's CPU baseline and the batched-vs-plain
-comparison on 512 uneven GI instances (--workload batch512 alone); --workload serve
-runs the continuous-batching server under Poisson arrivals.
+default line also carries the oracle's CPU baseline, the same anneal with int8
+operands (``int8``), the batched-vs-plain comparison on 512 uneven GI instances
+(--workload batch512 alone) and a compact served figure (``served``: saturation and
+one Poisson replay at 0.8 of it; --workload serve runs the full served workload).
 
 Prints one JSON line (rank 0).  --gpus N with N > 1 is refused: this build runs on
 one GPU; see the design notes for how trials would be sharded across GPUs.
@@ -71,6 +72,9 @@ def parse():
                     help="field-product operands of the main line (auto: fp4 when J is exactly representable)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison on 512 uneven GI instances")
+    ap.add_argument("--no-int8", action="store_true", help="skip the int8-operand timing of the main anneal")
+    ap.add_argument("--int8-steps", type=int, default=2, help="timed anneals with int8 operands")
+    ap.add_argument("--no-served", action="store_true", help="skip the compact served figure")
     ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (scale for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -105,7 +109,14 @@ def cpu_baseline(h, J, e_star, wl, q, i0, sample_cycles):
                 wl.delay, wl.seed, target=e_star)
     dt = time.perf_counter() - t0
     updates = wl.spins * wl.replicas * len(trials) * sample_cycles
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
     return {"value": updates / dt, "unit": "spin-updates/s", "cores": int(threads), "kind": "oracle",
+            "host_cpus": int(os.cpu_count() or 1), "host_cpus_usable": int(affinity),
+            "cores_note": "cores = BLAS threads the oracle's field product ran on (the rest of the oracle is "
+                          "single-threaded numpy)",
             "sample": f"trials 0-1 of {wl.trials}, cycles 0-{sample_cycles - 1} of {wl.cycles} "
                       f"({updates:.3g} spin updates in {dt:.1f} s; whole-job estimate "
                       f"{wl.spin_updates / (updates / dt):.0f} s)"}
@@ -185,6 +196,47 @@ def batched_vs_plain(args):
         "tts99_all_instances_plain_s": tts(plain_ms / 1e3, ps_min),
         "plain_equals_batched": bool(same),
     }
+
+
+def int8_line(prob, kw, out, stream, ops, updates, best_ref, steps):
+    """The same anneal with int8 operands (J as int8 planes, int32 accumulation): the arithmetic the
+    general-J path uses.  Timed like the main line with HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    import paper_2302_12454_amd as lib
+    lib.ssqa_anneal(prob, operand_format=1, stream=stream, out=out, **kw)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        lib.ssqa_anneal(prob, operand_format=1, stream=stream, out=out, **kw)
+        b.record(stream)
+    torch.cuda.synchronize()
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = sum(step_ms) / len(step_ms)
+    print(f"int8 operands: {', '.join(f'{x:.1f}' for x in step_ms)} ms", file=sys.stderr, flush=True)
+    same = bool(np.array_equal(out.best_energy.cpu().numpy(), best_ref))
+    return {"operands": "int8 planes, int32 accumulation", "steps": steps, "ms_per_step": ms,
+            "spin_updates_per_s": updates / (ms / 1e3), "achieved_tops": ops / (ms / 1e3) / 1e12,
+            "peak_tops": INT8_MFMA_PEAK / 1e12, "int8_mfma_frac": ops / (ms / 1e3) / INT8_MFMA_PEAK,
+            "best_equals_fp4_run": same}
+
+
+def served_line(args):
+    """A compact served figure for the default line: the serve workload's saturation run, then one
+    Poisson replay at 0.8 of that rate."""
+    saved = args.serve_load
+    args.serve_load = [0.8]
+    try:
+        res = serve_workload(args)
+    finally:
+        args.serve_load = saved
+    load = res["loads"][0]
+    return {"workload": res["workload"], "saturation_qps": res["saturation"]["qps"],
+            "saturation_latency_p99_s": res["saturation"]["latency_p99_s"],
+            "offered_load": load["offered_load"], "qps": load["qps"], "latency_p50_s": load["latency_p50_s"],
+            "latency_p99_s": load["latency_p99_s"], "spin_updates_per_s": load["spin_updates_per_s"],
+            "solved_fraction": load["solved_fraction"], "completed": load["completed"]}
 
 
 def serve_workload(args):
@@ -463,10 +515,11 @@ def main():
                            energy_trace=None, final_is=None)
     stream = torch.cuda.current_stream()
 
+    step_kwargs = dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=wl.alpha, noise_amp=noise,
+                       delay=wl.delay, seed=wl.seed, coupling_mode=wl.coupling_mode, target=e_star)
+
     def step():
-        lib.ssqa_anneal(prob, replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=wl.alpha, noise_amp=noise,
-                        delay=wl.delay, seed=wl.seed, coupling_mode=wl.coupling_mode, target=e_star,
-                        operand_format=fmt, stream=stream, out=out)
+        lib.ssqa_anneal(prob, operand_format=fmt, stream=stream, out=out, **step_kwargs)
 
     for w in range(args.warmup):
         step()
@@ -534,10 +587,15 @@ def main():
     if not args.no_cpu_baseline:
         num_j = np.asarray(J)
         result["cpu_baseline"] = cpu_baseline(h, num_j, e_star, wl, q, i0, args.cpu_sample_cycles)
+    if not args.no_int8 and args.workload == "gi50" and fmt != 1:
+        result["int8"] = int8_line(prob, step_kwargs, out, stream, ops, updates, best, args.int8_steps)
     if not args.no_batched and args.workload == "gi50":
         del out, prob
         torch.cuda.empty_cache()
         result["batched_vs_plain"] = batched_vs_plain(args)
+    if not args.no_served and args.workload == "gi50":
+        torch.cuda.empty_cache()
+        result["served"] = served_line(args)
     print(json.dumps(result), flush=True)
 
 

@@ -402,7 +402,11 @@ struct ssqa_batch {
 extern "C" {
 
 const char* ssqa_status_string(ssqa_status s) {
-    switch (s) {
+    // A C caller may pass any int; reading the argument's bits as an int avoids loading an enum value outside
+    // the enumeration's range, which C++ leaves undefined.
+    int v;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
         case SSQA_OK: return "SSQA_OK";
         case SSQA_EINVAL: return "SSQA_EINVAL";
         case SSQA_ENOMEM: return "SSQA_ENOMEM";
