@@ -72,6 +72,8 @@ def parse():
                     help="field-product operands of the main line (auto: fp4 when J is exactly representable)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison on 512 uneven GI instances")
+    ap.add_argument("--no-tune", action="store_true", help="built-in tiling rules instead of the autotuner")
+    ap.add_argument("--tune-cycles", type=int, default=20, help="cycles of each autotuner probe")
     ap.add_argument("--no-int8", action="store_true", help="skip the int8-operand timing of the main anneal")
     ap.add_argument("--int8-steps", type=int, default=2, help="timed anneals with int8 operands")
     ap.add_argument("--no-served", action="store_true", help="skip the compact served figure")
@@ -147,6 +149,12 @@ def batched_vs_plain(args):
         spins.append(len(h))
     print(f"built {len(jobs)} problems", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
+    tune = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tune = lib.ssqa_tune_batch(jobs, probe_cycles=args.tune_cycles, stream=stream)
+        tune["seconds"] = time.perf_counter() - t0
+        print(f"tuned batch: 128 columns from {tune['wide_rows']} padded rows", file=sys.stderr, flush=True)
     batch = lib.Batch(jobs)
     batch.run(stream)
     torch.cuda.synchronize()
@@ -195,6 +203,8 @@ def batched_vs_plain(args):
         "tts99_all_instances_batched_s": tts(batched_ms / 1e3, ps_min),
         "tts99_all_instances_plain_s": tts(plain_ms / 1e3, ps_min),
         "plain_equals_batched": bool(same),
+        "wide_rows": tune["wide_rows"] if tune else 1024, "tuned": tune is not None,
+        **({"autotuner": tune} if tune else {}),
     }
 
 
@@ -505,9 +515,6 @@ def main():
     prob = lib.Problem(h, J, device=0)
     N, R, T, SC = wl.spins, wl.replicas, wl.trials, wl.cycles
     fmt = {"auto": 0, "int8": 1, "fp4": 2}[args.operands]
-    if fmt == 0:
-        fmt = 2 if prob.fp4_exact else 1
-    dtype, peak = ("fp4", FP4_MFMA_PEAK) if fmt == 2 else ("int8", INT8_MFMA_PEAK)
 
     dev = torch.device("cuda", 0)
     out = lib.AnnealResult(best_energy=torch.empty(T, dtype=torch.int64, device=dev),
@@ -517,6 +524,21 @@ def main():
 
     step_kwargs = dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=wl.alpha, noise_amp=noise,
                        delay=wl.delay, seed=wl.seed, coupling_mode=wl.coupling_mode, target=e_star)
+
+    # The tiling: with automatic operands the autotuner times every legal tile on the first cycles of this
+    # anneal (outside the timed region) and the timed anneals take the fastest.
+    tune = None
+    if fmt == 0 and not args.no_tune:
+        t0 = time.perf_counter()
+        chosen, cands = lib.ssqa_tune_anneal(prob, probe_cycles=args.tune_cycles, stream=stream, **step_kwargs)
+        tune = {"candidates": len(cands), "probe_cycles": min(args.tune_cycles, SC),
+                "seconds": time.perf_counter() - t0,
+                "timed": [{k: c[k] for k in ("block_columns", "trials_per_block", "operands", "ms_per_cycle")}
+                          for c in cands]}
+        print(f"tuned: {chosen['block_columns']} columns x {chosen['trials_per_block']} trials, "
+              f"{chosen['operands']} ({len(cands)} candidates)", file=sys.stderr, flush=True)
+    tile, tuned = lib.ssqa_tune_lookup(prob, operand_format=fmt, **step_kwargs)
+    dtype, peak = ("fp4", FP4_MFMA_PEAK) if tile["operands"] == "fp4" else ("int8", INT8_MFMA_PEAK)
 
     def step():
         lib.ssqa_anneal(prob, operand_format=fmt, stream=stream, out=out, **step_kwargs)
@@ -573,6 +595,8 @@ def main():
                                f"(graph seed {wl.graph_seed}), R={R}, T={T}, SC={SC}, tau={wl.tau}, "
                                f"Philox seed {wl.seed}, plain form (one persistent launch per anneal)",
                    "spins": N, "replicas": R, "trials": T, "cycles": SC},
+        "tile": dict({k: tile[k] for k in ("block_columns", "trials_per_block", "operands", "blocks")},
+                     tuned=tuned, **({"autotuner": tune} if tune else {})),
         "p_s": p_s,
         "e_star": int(e_star),
         "tts99_s_per_trial_amortised": tts(sec / T),
@@ -587,7 +611,7 @@ def main():
     if not args.no_cpu_baseline:
         num_j = np.asarray(J)
         result["cpu_baseline"] = cpu_baseline(h, num_j, e_star, wl, q, i0, args.cpu_sample_cycles)
-    if not args.no_int8 and args.workload == "gi50" and fmt != 1:
+    if not args.no_int8 and args.workload == "gi50" and dtype != "int8":
         result["int8"] = int8_line(prob, step_kwargs, out, stream, ops, updates, best, args.int8_steps)
     if not args.no_batched and args.workload == "gi50":
         del out, prob

@@ -189,6 +189,70 @@ ssqa_status ssqa_anneal_noalloc(ssqa_problem_t problem, const ssqa_anneal_params
                                 const ssqa_anneal_outputs* outputs, void* hip_stream);
 
 /* ------------------------------------------------------------------------------------------- */
+/* Autotuner: the tiling of the field product (Section 3.2's parallel update of all N * R spins) */
+/* chosen by timing the legal candidates on the device.                                        */
+/* ------------------------------------------------------------------------------------------- */
+
+/* One tiling of an anneal: whole trials per workgroup of `block_columns` columns, and the operands of the
+ * field product.  A tiling changes only speed, never results. */
+typedef struct ssqa_tile {
+    int32_t block_columns;     /* 32, 64 or 128 columns (trial-replica pairs) per workgroup          */
+    int32_t trials_per_block;  /* 1 .. block_columns / R trials per workgroup                        */
+    int32_t operand_format;    /* 1 = int8 planes, 2 = fp4 (as ssqa_anneal_params.operand_format)     */
+    int32_t blocks;            /* workgroups of the launch: ceil(T / trials_per_block)               */
+    double ms_per_cycle;       /* measured device time per cycle (0 when not measured)               */
+} ssqa_tile;
+
+/*
+ * Time every legal tiling of the anneal `params` describes (block_columns and operand_format must be 0:
+ * the tuner chooses them) on its first min(cycles, probe_cycles) cycles, on `hip_stream`, and record the
+ * fastest in the process-wide cache under (device name, architecture and compute units; kernel build;
+ * padded N, planes, R, T, d, coupling mode, epilogue variant, whether fp4 is exact).  Candidates: 32, 64
+ * and 128 columns (128 with fp4 operands only) where the replicas and the LDS allow, whole-block packing
+ * and spreading the trials over 1, 2 or 4 workgroups per CU, fp4 (when exact) and int8 operands.  Up to
+ * `capacity` timed candidates are written to `candidates` (host array), their number to `count` (may be
+ * NULL), the chosen one to `chosen`.  Synchronises the stream; allocates and frees its own device memory.
+ * Afterwards ssqa_anneal and ssqa_anneal_noalloc take the recorded tiling for requests of this shape with
+ * block_columns = 0 and operand_format = 0.  Errors as for ssqa_anneal.
+ */
+ssqa_status ssqa_tune_anneal(ssqa_problem_t problem, const ssqa_anneal_params* params, int32_t probe_cycles,
+                             void* hip_stream, ssqa_tile* candidates, int32_t capacity, int32_t* count,
+                             ssqa_tile* chosen);
+
+/*
+ * Time the batched form of these anneals (arguments as for ssqa_batch_create, without outputs) on their first
+ * min(cycles, probe_cycles) cycles for every padded size from which automatic blocks could take 128
+ * columns (each distinct padded N of an anneal that could, and never), and record the fastest floor in the
+ * cache under (device, kernel build, the batch's shape).  `wide_rows` receives it (0 = never); ms_per_cycle
+ * (may be NULL) its time per cycle.  ssqa_batch_create then uses it for a batch of the same shape.
+ */
+ssqa_status ssqa_tune_batch(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
+                            int32_t probe_cycles, void* hip_stream, int32_t* wide_rows, double* ms_per_cycle);
+
+/* The tiling ssqa_anneal would use for `params` (a recorded one for automatic requests, else the built-in
+ * rules); `tuned` (may be NULL) receives 1 when it came from the cache.  No device work. */
+ssqa_status ssqa_tune_lookup(ssqa_problem_t problem, const ssqa_anneal_params* params, ssqa_tile* tile,
+                             int32_t* tuned);
+
+/* Record `tile` for the shape of `params` (block_columns = operand_format = 0) without timing it;
+ * SSQA_ENOTSUP when the tile cannot run that anneal. */
+ssqa_status ssqa_tune_set(ssqa_problem_t problem, const ssqa_anneal_params* params, const ssqa_tile* tile);
+
+/* Write every cached entry to a JSON file {"format": "ssqa-tune-1", "entries": [...]} (SSQA_EINVAL when it
+ * cannot be written).  Entries of other devices and kernel builds are kept and written too. */
+ssqa_status ssqa_tune_save(const char* path);
+
+/* Merge the entries of a file written by ssqa_tune_save into the cache (an entry replaces one of the same
+ * key); `loaded` (may be NULL) receives their number.  A file that does not parse, or any entry with a
+ * missing or out-of-range field, fails with SSQA_EINVAL and leaves the cache unchanged.  Entries apply only
+ * on the device and kernel build they name. */
+ssqa_status ssqa_tune_load(const char* path, int32_t* loaded);
+
+/* Number of cached entries; clearing the cache restores the built-in rules. */
+int32_t ssqa_tune_entries(void);
+void ssqa_tune_clear(void);
+
+/* ------------------------------------------------------------------------------------------- */
 /* Batched form: many anneals of uneven size in one persistent launch, replayed from a HIP graph.*/
 /* ------------------------------------------------------------------------------------------- */
 

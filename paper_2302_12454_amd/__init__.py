@@ -29,4 +29,12 @@ from .api import (  # noqa: F401
     ssqa_sa_schedule,
     ssqa_server_create,
     ssqa_ssa_i0_schedule,
+    ssqa_tune_anneal,
+    ssqa_tune_batch,
+    ssqa_tune_clear,
+    ssqa_tune_entries,
+    ssqa_tune_load,
+    ssqa_tune_lookup,
+    ssqa_tune_save,
+    ssqa_tune_set,
 )

@@ -115,6 +115,16 @@ class ServerStats(ctypes.Structure):
     ]
 
 
+class Tile(ctypes.Structure):
+    _fields_ = [
+        ("block_columns", ctypes.c_int32),
+        ("trials_per_block", ctypes.c_int32),
+        ("operand_format", ctypes.c_int32),
+        ("blocks", ctypes.c_int32),
+        ("ms_per_cycle", ctypes.c_double),
+    ]
+
+
 # Every symbol include/ssqa.h declares, with (restype, argtypes).
 SIGNATURES = {
     "ssqa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -130,6 +140,17 @@ SIGNATURES = {
                                    ctypes.POINTER(AnnealOutputs), ctypes.c_void_p]),
     "ssqa_anneal_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams),
                                            ctypes.POINTER(AnnealOutputs), ctypes.c_void_p]),
+    "ssqa_tune_anneal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.POINTER(Tile), ctypes.c_int32, c_int32_p, ctypes.POINTER(Tile)]),
+    "ssqa_tune_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(AnnealParams),
+                                       ctypes.c_int32, ctypes.c_void_p, c_int32_p, ctypes.POINTER(ctypes.c_double)]),
+    "ssqa_tune_lookup": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams), ctypes.POINTER(Tile),
+                                        c_int32_p]),
+    "ssqa_tune_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AnnealParams), ctypes.POINTER(Tile)]),
+    "ssqa_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "ssqa_tune_load": (ctypes.c_int, [ctypes.c_char_p, c_int32_p]),
+    "ssqa_tune_entries": (ctypes.c_int32, []),
+    "ssqa_tune_clear": (None, []),
     "ssqa_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p]),
     "ssqa_qmc_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,

@@ -8,6 +8,7 @@ host code.  PyTorch supplies device memory and the current HIP stream.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -274,6 +275,95 @@ class Batch:
 
 def ssqa_batch_create(jobs) -> Batch:
     return Batch(jobs)
+
+
+def _tile_dict(t) -> dict:
+    return {"block_columns": int(t.block_columns), "trials_per_block": int(t.trials_per_block),
+            "operands": "fp4" if t.operand_format == 2 else "int8", "blocks": int(t.blocks),
+            "ms_per_cycle": float(t.ms_per_cycle)}
+
+
+def _anneal_params_only(kw: dict):
+    kw = dict(kw)
+    for key in ("trace", "final_is", "stream", "out", "stop_cycle", "resume", "checkpoint"):
+        kw.pop(key, None)
+    return _params(**kw)
+
+
+def ssqa_tune_anneal(problem: Problem, *, probe_cycles: int = 20, stream=None, **anneal):
+    """ssqa_tune_anneal: time every legal tiling of this anneal (ssqa_anneal's keyword arguments, with
+    block_columns and operand_format left automatic) on its first ``probe_cycles`` cycles and record the
+    fastest.  Returns (chosen, candidates) as dicts."""
+    lib = _lib.load()
+    p, keep = _anneal_params_only(anneal)
+    cap = 64
+    cands = (_lib.Tile * cap)()
+    count = ctypes.c_int32()
+    chosen = _lib.Tile()
+    _check(lib.ssqa_tune_anneal(problem.handle, ctypes.byref(p), int(probe_cycles), _stream_handle(stream), cands, cap,
+                                ctypes.byref(count), ctypes.byref(chosen)), "ssqa_tune_anneal")
+    del keep
+    return _tile_dict(chosen), [_tile_dict(cands[i]) for i in range(min(count.value, cap))]
+
+
+def ssqa_tune_batch(jobs, *, probe_cycles: int = 20, stream=None) -> dict:
+    """ssqa_tune_batch over (problem, kwargs) jobs as for Batch: the fastest 128-column floor (0 = never)."""
+    lib = _lib.load()
+    n = len(jobs)
+    params = (_lib.AnnealParams * n)()
+    handles = (ctypes.c_void_p * n)()
+    keep = []
+    for i, (prob, kw) in enumerate(jobs):
+        p, k = _anneal_params_only(kw)
+        params[i] = p
+        handles[i] = prob.handle
+        keep.append(k)
+    rows = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(lib.ssqa_tune_batch(n, handles, params, int(probe_cycles), _stream_handle(stream), ctypes.byref(rows),
+                               ctypes.byref(ms)), "ssqa_tune_batch")
+    del keep
+    return {"wide_rows": int(rows.value), "ms_per_cycle": float(ms.value)}
+
+
+def ssqa_tune_lookup(problem: Problem, **anneal):
+    """The tiling ssqa_anneal would take for these arguments, and whether the tuner's cache chose it."""
+    lib = _lib.load()
+    p, keep = _anneal_params_only(anneal)
+    t = _lib.Tile()
+    tuned = ctypes.c_int32()
+    _check(lib.ssqa_tune_lookup(problem.handle, ctypes.byref(p), ctypes.byref(t), ctypes.byref(tuned)),
+           "ssqa_tune_lookup")
+    del keep
+    return _tile_dict(t), bool(tuned.value)
+
+
+def ssqa_tune_set(problem: Problem, tile: dict, **anneal) -> None:
+    """Record ``tile`` (block_columns, trials_per_block, operands) for the shape of these anneal arguments."""
+    lib = _lib.load()
+    p, keep = _anneal_params_only(anneal)
+    t = _lib.Tile(int(tile["block_columns"]), int(tile["trials_per_block"]),
+                  2 if tile.get("operands", "int8") == "fp4" else 1, 0, float(tile.get("ms_per_cycle", 0.0)))
+    _check(lib.ssqa_tune_set(problem.handle, ctypes.byref(p), ctypes.byref(t)), "ssqa_tune_set")
+    del keep
+
+
+def ssqa_tune_save(path: str) -> None:
+    _check(_lib.load().ssqa_tune_save(os.fsencode(path)), "ssqa_tune_save")
+
+
+def ssqa_tune_load(path: str) -> int:
+    n = ctypes.c_int32()
+    _check(_lib.load().ssqa_tune_load(os.fsencode(path), ctypes.byref(n)), "ssqa_tune_load")
+    return int(n.value)
+
+
+def ssqa_tune_entries() -> int:
+    return int(_lib.load().ssqa_tune_entries())
+
+
+def ssqa_tune_clear() -> None:
+    _lib.load().ssqa_tune_clear()
 
 
 def ssqa_energy(problem: Problem, spins, stream=None):

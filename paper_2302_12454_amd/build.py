@@ -2,6 +2,7 @@
 
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -14,7 +15,18 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libssqa.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["sweep.hip", "sa.hip", "api.cpp", "host.cpp", "server.cpp"]
+SOURCES = ["sweep.hip", "sa.hip", "api.cpp", "host.cpp", "server.cpp", "tune.cpp"]
+# The autotuner's cache entries are valid for one build of the sweep kernel: they carry this digest.
+KERNEL_SOURCES = ["sweep.hip", "internal.hpp", "philox.hpp"]
+
+
+def kernel_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the sweep kernel's sources."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 ARCH = "gfx950"
 
 
@@ -32,7 +44,7 @@ def build(verbose: bool = False) -> str:
     common = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
               # packed FP32 instructions are kept out of every kernel
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-Wall", "-Wno-unused-function"]
+              "-Wall", "-Wno-unused-function", f'-DSSQA_KERNEL_HASH="{kernel_hash()}"']
     objs = []
     for src in SOURCES:
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")

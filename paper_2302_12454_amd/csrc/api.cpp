@@ -189,34 +189,53 @@ int device_xcd_count(int device) {
 }
 
 // Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
-// block, bit planes that fit in LDS, and at least 1024 padded rows (1536 for a plain anneal, `plain`).  With
-// fewer rows the K loop of a tile is short and two 64-column workgroups per CU hide its latency better than
-// one of 128 columns; a plain anneal, which has the chip to itself, gains from 1536 rows on, a batch, whose
-// many matrices share each L2, already from 1024 (the halved J traffic per MFMA counts for more there).
-static bool wide_blocks_pay(const ssqa_problem* prob, const ssqa_anneal_params* pa, bool plain) {
+// block, bit planes that fit in LDS, and at least `min_rows` padded rows (0: never).  With fewer rows the K
+// loop of a tile is short and two 64-column workgroups per CU hide its latency better than one of 128
+// columns; a plain anneal, which has the chip to itself, gains from 1536 rows on, a batch, whose many
+// matrices share each L2, already from 1024 (the halved J traffic per MFMA counts for more there).
+static bool wide_blocks_pay(const ssqa_problem* prob, const ssqa_anneal_params* pa, int min_rows) {
     const int np = prob->dev.np;
-    return pa->block_columns == 0 && block_columns(prob, pa) == 64 && use_fp4(prob, pa) &&
-           128 % pa->replicas == 0 && np >= (plain ? 1536 : 1024) &&
-           sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
+    return min_rows > 0 && pa->block_columns == 0 && block_columns(prob, pa) == 64 && use_fp4(prob, pa) &&
+           128 % pa->replicas == 0 && np >= min_rows && sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
 }
 
-// Layout of a plain anneal.  Packing whole workgroups (as many trials as fit) gives the best J reuse
-// once there are enough workgroups for every CU twice over; a smaller anneal is spread instead (the
-// narrow block when the replicas fit it, and fewer trials per workgroup, leaving columns unused), so
-// that its latency is not set by a handful of CUs.  Results do not depend on the layout.
-PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+bool batch_wide(const ssqa_problem* prob, const ssqa_anneal_params* pa, int min_rows) {
+    return wide_blocks_pay(prob, pa, min_rows);
+}
+
+bool tile_legal(const ssqa_problem* prob, const ssqa_anneal_params* pa, int nb, int tpw, bool fp4) {
+    if (nb != 32 && nb != 64 && nb != 128) return false;
+    if (pa->replicas > nb || tpw < 1 || tpw > nb / pa->replicas) return false;
+    if (fp4 && !use_fp4(prob, pa)) return false;
+    if (nb == 128 && !fp4) return false;
+    return sweep_lds_bytes(prob->dev.np, pa->delay, nb) <= 160 * 1024;
+}
+
+// Layout of a plain anneal by the built-in rules.  Packing whole workgroups (as many trials as fit) gives
+// the best J reuse once there are enough workgroups for every CU twice over; a smaller anneal is spread
+// instead (the narrow block when the replicas fit it, and fewer trials per workgroup, leaving columns
+// unused), so that its latency is not set by a handful of CUs.  Results do not depend on the layout.
+PlainLayout rule_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
     const int R = pa->replicas, T = pa->trials;
     const int target = 2 * device_cu_count(prob->device);
+    const bool fp4 = use_fp4(prob, pa);
     int nb = block_columns(prob, pa);
     // With fp4 operands, 128 columns per workgroup (one per CU, one wave per SIMD with 512 registers) feed each
     // J fragment to twice as many MFMAs; taken when wide blocks pay and still number two per CU.
-    if (wide_blocks_pay(prob, pa, true) && (T + 128 / R - 1) / (128 / R) >= target)
-        return PlainLayout{128, 128 / R, (T + 128 / R - 1) / (128 / R)};
+    if (wide_blocks_pay(prob, pa, 1536) && (T + 128 / R - 1) / (128 / R) >= target)
+        return PlainLayout{128, 128 / R, (T + 128 / R - 1) / (128 / R), fp4, false};
     if (pa->block_columns == 0 && nb == 64 && R <= 32 && (T + 64 / R - 1) / (64 / R) < target) nb = 32;
     const int full = nb / R;
     int tpw = full;
     if ((T + full - 1) / full < target) tpw = std::max(1, (T + target - 1) / target);
-    return PlainLayout{nb, tpw, (T + tpw - 1) / tpw};
+    return PlainLayout{nb, tpw, (T + tpw - 1) / tpw, fp4, false};
+}
+
+PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
+    TunedTile t;
+    if (pa->block_columns == 0 && pa->operand_format == 0 && tuned_plain(prob, pa, &t))
+        return PlainLayout{t.nb, t.tpw, (pa->trials + t.tpw - 1) / t.tpw, t.fp4 != 0, true};
+    return rule_layout(prob, pa);
 }
 
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out) {
@@ -257,13 +276,14 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
 }
 
 SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
-                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist, int nb, int tpw) {
+                    const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist, int nb, int tpw,
+                    int fp4) {
     SweepArgs a{};
     if (nb == 0) nb = block_columns(prob, pa);
     if (tpw == 0) tpw = nb / pa->replicas;
     a.prob = prob->dev;
     a.nb = nb;
-    a.fp4 = use_fp4(prob, pa) ? 1 : 0;
+    a.fp4 = fp4 < 0 ? (use_fp4(prob, pa) ? 1 : 0) : (fp4 ? 1 : 0);
     a.fast = fast_epilogue(pa) ? 1 : 0;
     a.R = pa->replicas;
     a.T = pa->trials;
@@ -355,7 +375,7 @@ ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, 
         e = launch_import_state(pa->resume->counters, pa->resume->history, prob->dev.n, np, R, T, tpw, nb, pa->delay,
                                 is_state, hist, stream);
     if (e == hipSuccess) {
-        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist, nb, tpw);
+        SweepArgs a = make_args(prob, pa, out, d_jperp, d_i0, is_state, hist, nb, tpw, z.layout.fp4 ? 1 : 0);
         const int chunk = pa->cycles_per_launch > 0 ? pa->cycles_per_launch : std::max(t1 - t0, 1);
         int t = t0;
         do {
@@ -541,14 +561,25 @@ ssqa_status ssqa_anneal_noalloc(ssqa_problem_t prob, const ssqa_anneal_params* p
     return anneal_impl(prob, pa, out, reinterpret_cast<hipStream_t>(hip_stream), &ws);
 }
 
-ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
-                              const ssqa_anneal_outputs* outputs, ssqa_batch_t* out) {
-    g_last_error.clear();
+}  // extern "C"
+
+namespace ssqa {
+namespace detail {
+
+ssqa_status batch_create_impl(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
+                              const ssqa_anneal_outputs* outputs, ssqa_batch_t* out, int wide_rows) {
     if (!out) return fail(SSQA_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || count > 65535) return fail(SSQA_EINVAL, "count = %d outside [1, 65535]", count);
     if (!problems || !params || !outputs) return fail(SSQA_EINVAL, "NULL problems, params or outputs");
     const int device = problems[0] ? problems[0]->device : -1;
+    // 128-column floor: the caller's, else the autotuner's for this batch, else the built-in one
+    if (wide_rows < 0 && problems[0]) {
+        bool all = true;
+        for (int i = 0; i < count && all; ++i) all = problems[i] != nullptr;
+        if (all) wide_rows = tuned_batch_rows(device, batch_signature(count, problems, params));
+    }
+    if (wide_rows < 0) wide_rows = kBatchWideRows;
     // sizes and validation
     size_t sched_words = 0, is_bytes = 0;
     std::vector<int> n_wg(count), tpw(count), nbs(count);
@@ -565,7 +596,7 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
         if (params[i].start_cycle != 0 || (params[i].stop_cycle != 0 && params[i].stop_cycle != params[i].cycles) ||
             outputs[i].checkpoint)
             return fail(SSQA_EINVAL, "anneal %d: start_cycle, stop_cycle and checkpoint are for ssqa_anneal", i);
-        nbs[i] = wide_blocks_pay(p, &params[i], false) ? 128 : block_columns(p, &params[i]);
+        nbs[i] = wide_blocks_pay(p, &params[i], wide_rows) ? 128 : block_columns(p, &params[i]);
         tpw[i] = nbs[i] / params[i].replicas;
         n_wg[i] = (params[i].trials + tpw[i] - 1) / tpw[i];
         if (n_wg[i] > 65535) return fail(SSQA_ENOTSUP, "anneal %d needs more than 65535 blocks", i);
@@ -673,6 +704,17 @@ ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, con
     b->blocks = (int)work.size();
     *out = b;
     return SSQA_OK;
+}
+
+}  // namespace detail
+}  // namespace ssqa
+
+extern "C" {
+
+ssqa_status ssqa_batch_create(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
+                              const ssqa_anneal_outputs* outputs, ssqa_batch_t* out) {
+    g_last_error.clear();
+    return batch_create_impl(count, problems, params, outputs, out, -1);
 }
 
 ssqa_status ssqa_batch_run(ssqa_batch_t b, void* hip_stream) {

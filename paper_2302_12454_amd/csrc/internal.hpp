@@ -194,6 +194,8 @@ struct DeviceGuard {
 
 // Whether the fp4 field product of an anneal of `prob` with `pa` is exact (schedules already checked).
 bool fp4_fits(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// Whether the byte-parallel epilogue applies to `pa` over its whole schedule (alpha = 1 and small increments).
+bool fast_epilogue(const ssqa_anneal_params* pa);
 // Whether an anneal of `prob` with `pa` runs its field product on the fp4 copy of J.
 bool use_fp4(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Columns per workgroup for an anneal of `prob` with `pa`: the requested 32, 64 or 128, else 64 or 32.
@@ -203,15 +205,45 @@ int block_columns_for(int np, const ssqa_anneal_params* pa);
 // Full argument check of one anneal; records the reason on failure.
 ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out);
 // Kernel arguments of one anneal (t_begin / t_end / final_pass left for the caller).  nb and tpw
-// (columns and trials per workgroup) default to the packed layout of block_columns when 0.
+// (columns and trials per workgroup) default to the packed layout of block_columns when 0; fp4 < 0 takes the
+// operands use_fp4 picks, else 1 = fp4, 0 = int8 planes.
 SweepArgs make_args(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
                     const int32_t* d_jperp, const int32_t* d_i0, int8_t* is_state, uint32_t* hist, int nb = 0,
-                    int tpw = 0);
-// Workgroup layout of a plain anneal (ssqa_anneal): columns and trials per workgroup, workgroups.
+                    int tpw = 0, int fp4 = -1);
+// Workgroup layout of a plain anneal (ssqa_anneal): columns and trials per workgroup, workgroups, operands, and
+// whether the autotuner's cache chose it.
 struct PlainLayout {
     int nb, tpw, n_wg;
+    bool fp4, tuned;
 };
+// The built-in rules, or, for an automatic request (block_columns = 0, operand_format = 0), the tile the
+// autotuner recorded for this device, kernel build and shape when there is one.
 PlainLayout plain_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// The built-in rules alone.
+PlainLayout rule_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa);
+// Whether a tile (nb columns and tpw trials per workgroup, fp4 or int8 operands) can run `pa` on `prob`.
+bool tile_legal(const ssqa_problem* prob, const ssqa_anneal_params* pa, int nb, int tpw, bool fp4);
+// Whether an automatic block of a batch instance widens to 128 columns, with the padded-row floor `min_rows`
+// (0: never).
+bool batch_wide(const ssqa_problem* prob, const ssqa_anneal_params* pa, int min_rows);
+// Built-in floor of the batched form (padded rows from which automatic blocks take 128 columns).
+constexpr int kBatchWideRows = 1024;
+
+// Autotuner cache (tune.cpp).  A tile recorded for (device, kernel build, padded N, planes, R, T, delay, mode,
+// epilogue, fp4 availability); false when none applies.
+struct TunedTile {
+    int nb, tpw, fp4;
+    double ms_per_cycle;
+};
+bool tuned_plain(const ssqa_problem* prob, const ssqa_anneal_params* pa, TunedTile* out);
+// Identity of a batch's shape (padded N, planes, R, T, delay, mode, epilogue and fp4 availability of each
+// anneal, in order) for the cache.
+uint64_t batch_signature(int count, const ssqa_problem_t* problems, const ssqa_anneal_params* params);
+// The 128-column floor recorded for a batch of this signature on this device and build, or -1.
+int tuned_batch_rows(int device, uint64_t signature);
+// ssqa_batch_create with the 128-column floor `wide_rows` (< 0: the recorded floor, else the built-in one).
+ssqa_status batch_create_impl(int32_t count, const ssqa_problem_t* problems, const ssqa_anneal_params* params,
+                              const ssqa_anneal_outputs* outputs, ssqa_batch_t* out, int wide_rows);
 // Device state of one plain anneal: counters, bit-plane history and the two schedules ([jperp | i0]).
 struct AnnealSizes {
     PlainLayout layout;

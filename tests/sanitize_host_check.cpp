@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <random>
 #include <vector>
 
@@ -200,13 +201,55 @@ static void abi_checks() {
     EXPECT(ssqa_server_create(&cfg, &s) == SSQA_EINVAL);
 }
 
-int main() {
+// The autotuner's cache reader on a valid file, on every prefix of it (each must be refused) and on a few
+// malformed variants; then a save / load round trip.
+static void tune_cache(const char* dir) {
+    const std::string path = std::string(dir) + "/tune_cache.json";
+    const std::string good =
+        "{\"format\": \"ssqa-tune-1\", \"entries\": [\n"
+        "  {\"form\": \"plain\", \"device\": \"dev\\\"x\", \"kernel\": \"k\", \"np\": 256, \"planes\": 1, "
+        "\"replicas\": 8, \"trials\": 64, \"delay\": 1, \"mode\": 0, \"fast\": 1, \"fp4_ok\": 1, "
+        "\"block_columns\": 64, \"trials_per_block\": 8, \"operand_format\": 2, \"ms_per_cycle\": 1.5e-2},\n"
+        "  {\"form\": \"batch\", \"device\": \"dev\", \"kernel\": \"k\", \"signature\": \"0123456789abcdef\", "
+        "\"instances\": 3, \"wide_rows\": 0, \"ms_per_cycle\": 0, \"extra\": [true, false, null, {}]}\n]}\n";
+    auto write = [&path](const std::string& text) {
+        FILE* f = std::fopen(path.c_str(), "wb");
+        if (!f) return false;
+        std::fwrite(text.data(), 1, text.size(), f);
+        std::fclose(f);
+        return true;
+    };
+    ssqa_tune_clear();
+    int32_t n = -1;
+    EXPECT(write(good) && ssqa_tune_load(path.c_str(), &n) == SSQA_OK && n == 2);
+    EXPECT(ssqa_tune_entries() == 2);
+    const size_t body = good.size() - 2;   // without the closing brace and newline
+    for (size_t len = 0; len < body; ++len) {
+        EXPECT(write(good.substr(0, len)));
+        EXPECT(ssqa_tune_load(path.c_str(), &n) == SSQA_EINVAL);
+    }
+    for (const char* bad : {"{", "[", "\"", "{\"format\": \"ssqa-tune-1\", \"entries\": [{\"form\": 1}]}",
+                            "{\"a\": [[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[1]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]}",
+                            "{\"format\": \"ssqa-tune-1\", \"entries\": [], \"x\": \"\\u0041\"}", "-", "1e999"}) {
+        EXPECT(write(bad));
+        EXPECT(ssqa_tune_load(path.c_str(), &n) == SSQA_EINVAL);
+    }
+    EXPECT(ssqa_tune_entries() == 2);
+    EXPECT(ssqa_tune_save(path.c_str()) == SSQA_OK);
+    ssqa_tune_clear();
+    EXPECT(ssqa_tune_load(path.c_str(), &n) == SSQA_OK && n == 2);
+    ssqa_tune_clear();
+    EXPECT(ssqa_tune_load(nullptr, &n) == SSQA_EINVAL && ssqa_tune_save(nullptr) == SSQA_EINVAL);
+}
+
+int main(int argc, char** argv) {
     std::mt19937 rng(12345);
     schedules();
     gi_mapping(rng);
     philox();
     work_order(rng);
     abi_checks();
+    tune_cache(argc > 1 ? argv[1] : ".");
     if (g_bad) {
         std::printf("%d checks failed\n", g_bad);
         return 1;

@@ -186,7 +186,7 @@ def test_struct_layouts_match_header(tmp_path):
         "ssqa_anneal_outputs": lib_mod.AnnealOutputs, "ssqa_sa_params": lib_mod.SAParams,
         "ssqa_sa_outputs": lib_mod.SAOutputs, "ssqa_server_config": lib_mod.ServerConfig,
         "ssqa_request": lib_mod.Request, "ssqa_request_info": lib_mod.RequestInfo,
-        "ssqa_server_stats_t": lib_mod.ServerStats,
+        "ssqa_server_stats_t": lib_mod.ServerStats, "ssqa_tile": lib_mod.Tile,
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ssqa.h"', "int main(void) {"]
     for cname, cls in structs.items():

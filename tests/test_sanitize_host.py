@@ -1,9 +1,9 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer (no GPU needed).
 
-api.cpp, host.cpp and server.cpp (the C ABI's argument checks, the schedules, the graph-isomorphism mapping,
-the server's submit path) and work_order.hpp are compiled for the host only with -fsanitize=address,undefined
-(no recovery from undefined behaviour) and linked with the kernels' regular objects into
-tests/sanitize_host_check.cpp, which drives every path that runs without a device.  A sanitizer report aborts
+api.cpp, host.cpp, server.cpp and tune.cpp (the C ABI's argument checks, the schedules, the graph-isomorphism
+mapping, the server's submit path, the autotuner's cache reader) and work_order.hpp are compiled for the host
+only with -fsanitize=address,undefined (no recovery from undefined behaviour) and linked with the kernels'
+regular objects into tests/sanitize_host_check.cpp, which drives every path that runs without a device.  A sanitizer report aborts
 the program, so the test passes only on a clean run that prints "ok"."""
 
 import os
@@ -36,7 +36,7 @@ def test_host_code_under_asan_and_ubsan(tmp_path):
         b.build()
     objs = []
     common = ["-O1", "-g", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SAN]
-    for src in ("api.cpp", "host.cpp", "server.cpp"):
+    for src in ("api.cpp", "host.cpp", "server.cpp", "tune.cpp"):
         obj = str(tmp_path / (src + ".o"))
         subprocess.run([cc, *common, "-x", "hip", "--cuda-host-only", "--offload-arch=gfx950", "-c",
                         os.path.join(CSRC, src), "-o", obj], check=True, capture_output=True)
@@ -48,5 +48,5 @@ def test_host_code_under_asan_and_ubsan(tmp_path):
     subprocess.run([cc, *SAN, "--offload-arch=gfx950", drv, *objs, *kernels, "-o", exe], check=True,
                    capture_output=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
-    res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    res = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, env=env, timeout=300)
     assert res.returncode == 0 and res.stdout.strip().endswith("ok"), res.stdout[-3000:] + res.stderr[-3000:]
