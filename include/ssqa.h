@@ -124,13 +124,15 @@ typedef struct ssqa_anneal_params {
     const int32_t* i0;         /* host int32 [cycles]: I_0(t), 1 <= alpha <= I_0(t) <= 127     */
     uint64_t seed;             /* Philox key                                                    */
     int64_t target_energy;     /* E* for first_hit, or SSQA_NO_TARGET                           */
-    int32_t block_columns;     /* columns (whole trials) per workgroup: 0 = automatic (64 when R <= 64
-                                  and the bit planes fit in LDS, else 32; with fp4 operands 128 when
-                                  R divides 128, the problem pads to at least 1024 rows (1536 for
-                                  ssqa_anneal, which also needs at least two 128-column blocks per
-                                  CU) and the planes fit in LDS), or
-                                  32 / 64 / 128 (128 needs fp4 operands, else
-                                  SSQA_ENOTSUP).  A tiling choice only: results do not depend on it */
+    int32_t block_columns;     /* columns (whole trials) per workgroup: 0 = automatic (a tiling the
+                                  autotuner recorded for this shape, else: 64 when R <= 64 and the
+                                  bit planes fit in LDS, else 32; 128 when the operands are fp4 or J
+                                  fits one int8 plane, R divides 128, the problem pads to at least
+                                  1024 rows (1536 for ssqa_anneal, which also needs at least two
+                                  128-column blocks per CU) and the planes fit in LDS), or
+                                  32 / 64 / 128 (128 with int8 operands needs every |J_ij| <= 127,
+                                  else SSQA_ENOTSUP).  A tiling choice only: results do not depend
+                                  on it                                                            */
     int32_t operand_format;    /* field-product operands: 0 = automatic (fp4 when the problem has an
                                   fp4 copy and B + n_rnd + (1 + mode) max_t |J_perp(t)| + 128 < 2^22,
                                   see ssqa_create_problem, else int8 planes); 1 = int8 planes; 2 = fp4
@@ -208,8 +210,9 @@ typedef struct ssqa_tile {
  * the tuner chooses them) on its first min(cycles, probe_cycles) cycles, on `hip_stream`, and record the
  * fastest in the process-wide cache under (device name, architecture and compute units; kernel build;
  * padded N, planes, R, T, d, coupling mode, epilogue variant, whether fp4 is exact).  Candidates: 32, 64
- * and 128 columns (128 with fp4 operands only) where the replicas and the LDS allow, whole-block packing
- * and spreading the trials over 1, 2 or 4 workgroups per CU, fp4 (when exact) and int8 operands.  Up to
+ * and 128 columns (128 with int8 operands for single-plane J only) where the replicas and the LDS allow,
+ * whole-block packing and spreading the trials over 1, 2 or 4 workgroups per CU, fp4 (when exact) and int8
+ * operands.  Up to
  * `capacity` timed candidates are written to `candidates` (host array), their number to `count` (may be
  * NULL), the chosen one to `chosen`.  Synchronises the stream; allocates and frees its own device memory.
  * Afterwards ssqa_anneal and ssqa_anneal_noalloc take the recorded tiling for requests of this shape with

@@ -188,15 +188,16 @@ int device_xcd_count(int device) {
     return v;
 }
 
-// Whether an automatic 64-column block may widen to 128 columns: fp4 operands, whole trials filling the
-// block, bit planes that fit in LDS, and at least `min_rows` padded rows (0: never).  With fewer rows the K
+// Whether an automatic 64-column block may widen to 128 columns: fp4 operands or J in one int8 plane, whole
+// trials filling the block, bit planes that fit in LDS, and at least `min_rows` padded rows (0: never).  With fewer rows the K
 // loop of a tile is short and two 64-column workgroups per CU hide its latency better than one of 128
 // columns; a plain anneal, which has the chip to itself, gains from 1536 rows on, a batch, whose many
 // matrices share each L2, already from 1024 (the halved J traffic per MFMA counts for more there).
 static bool wide_blocks_pay(const ssqa_problem* prob, const ssqa_anneal_params* pa, int min_rows) {
     const int np = prob->dev.np;
-    return min_rows > 0 && pa->block_columns == 0 && block_columns(prob, pa) == 64 && use_fp4(prob, pa) &&
-           128 % pa->replicas == 0 && np >= min_rows && sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
+    return min_rows > 0 && pa->block_columns == 0 && block_columns(prob, pa) == 64 &&
+           (use_fp4(prob, pa) || prob->dev.planes == 1) && 128 % pa->replicas == 0 && np >= min_rows &&
+           sweep_lds_bytes(np, pa->delay, 128) <= 160 * 1024;
 }
 
 bool batch_wide(const ssqa_problem* prob, const ssqa_anneal_params* pa, int min_rows) {
@@ -207,7 +208,7 @@ bool tile_legal(const ssqa_problem* prob, const ssqa_anneal_params* pa, int nb, 
     if (nb != 32 && nb != 64 && nb != 128) return false;
     if (pa->replicas > nb || tpw < 1 || tpw > nb / pa->replicas) return false;
     if (fp4 && !use_fp4(prob, pa)) return false;
-    if (nb == 128 && !fp4) return false;
+    if (nb == 128 && !fp4 && prob->dev.planes != 1) return false;
     return sweep_lds_bytes(prob->dev.np, pa->delay, nb) <= 160 * 1024;
 }
 
@@ -220,8 +221,8 @@ PlainLayout rule_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa) 
     const int target = 2 * device_cu_count(prob->device);
     const bool fp4 = use_fp4(prob, pa);
     int nb = block_columns(prob, pa);
-    // With fp4 operands, 128 columns per workgroup (one per CU, one wave per SIMD with 512 registers) feed each
-    // J fragment to twice as many MFMAs; taken when wide blocks pay and still number two per CU.
+    // 128 columns per workgroup (one per CU, one wave per SIMD with 512 registers) feed each J fragment to twice
+    // as many MFMAs; taken when wide blocks pay and still number two per CU.
     if (wide_blocks_pay(prob, pa, 1536) && (T + 128 / R - 1) / (128 / R) >= target)
         return PlainLayout{128, 128 / R, (T + 128 / R - 1) / (128 / R), fp4, false};
     if (pa->block_columns == 0 && nb == 64 && R <= 32 && (T + 64 / R - 1) / (64 / R) < target) nb = 32;
@@ -265,10 +266,11 @@ ssqa_status check_params(const ssqa_problem* prob, const ssqa_anneal_params* pa,
     if (pa->operand_format == 2 && !fp4_fits(prob, pa))
         return fail(SSQA_ENOTSUP, "fp4 operands requested but max_i(|h_i| + 2 sum_j |J_ij|) + n_rnd + "
                                   "(1 + mode) max|jperp| + 128 >= 2^22: fp32 accumulation would not be exact");
-    if (pa->block_columns == 128 && !use_fp4(prob, pa))
-        return fail(SSQA_ENOTSUP, "128 columns per workgroup need fp4 operands");
     const int nb = block_columns(prob, pa);
     if (R > nb) return fail(SSQA_ENOTSUP, "replicas = %d exceeds %d columns per workgroup", R, nb);
+    if (nb == 128 && !use_fp4(prob, pa) && prob->dev.planes != 1)
+        return fail(SSQA_ENOTSUP, "128 columns per workgroup with int8 operands need every |J_ij| <= 127 "
+                                  "(one int8 plane); this J needs %d", prob->dev.planes);
     if (sweep_lds_bytes(prob->dev.np, pa->delay, nb) > 160 * 1024)
         return fail(SSQA_ENOTSUP, "N = %d with delay %d needs %zu bytes of LDS per workgroup (> 160 KiB)",
                     prob->dev.n, pa->delay, sweep_lds_bytes(prob->dev.np, pa->delay, nb));

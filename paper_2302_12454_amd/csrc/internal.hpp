@@ -103,9 +103,8 @@ hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t
 hipError_t configure_sweep_kernels();
 // Dynamic LDS of one sweep workgroup for padded size np, delay d and nb columns.
 size_t sweep_lds_bytes(int np, int delay, int nb);
-// Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.  nb = 128
-// exists with fp4 operands only (-1 otherwise).
-constexpr int kSweepVariants = 20;
+// Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.
+constexpr int kSweepVariants = 24;
 int sweep_variant(bool fast, int mode, int nb, bool fp4);
 // Columns per workgroup of a variant.
 int variant_columns(int variant);

@@ -72,12 +72,13 @@ __device__ __forceinline__ v4i expand_operand_fp4(uint32_t w) {
 __device__ __forceinline__ v8i widen(const v4i& x) { return __builtin_shufflevector(x, x, 0, 1, 2, 3, -1, -1, -1, -1); }
 
 __device__ __forceinline__ v4i expand_operand(uint32_t w) {
-    // w already shifted by 4 h; bytes are x = (sigma + 1) / 2 in {0, 1}
+    // w already shifted by 4 h; bytes are 2 x = sigma + 1 in {0, 2}, so that the int32 accumulator collects
+    // 2 sum_j J_ij x_j directly (as the fp4 product does through its scale)
     v4i r;
-    r[0] = (int)(w & 0x01010101u);
-    r[1] = (int)((w >> 1) & 0x01010101u);
-    r[2] = (int)((w >> 2) & 0x01010101u);
-    r[3] = (int)((w >> 3) & 0x01010101u);
+    r[0] = (int)((w << 1) & 0x02020202u);
+    r[1] = (int)(w & 0x02020202u);
+    r[2] = (int)((w >> 1) & 0x02020202u);
+    r[3] = (int)((w >> 2) & 0x02020202u);
     return r;
 }
 
@@ -190,14 +191,12 @@ __device__ __forceinline__ void prefetch_counters(v4i (&cnt)[kNBF][2], const int
     for (int f = 0; f < kNBF && f < cnt_ahead<kFp4>(); ++f) load_counters<kFp4>(cnt[f], is_lane, np, f);
 }
 
-// 4 rows of the tile's row vectors: lane l < 32 takes h - rowsum at rows 4 l .. 4 l + 3, lane l >= 32 takes
-// h (fp4 operands) or 2 h - rowsum (int8 operands) at rows 4 (l - 32) .. 4 (l - 32) + 3.
-template <bool kFp4>
+// 4 rows of the tile's row vectors: lane l < 32 takes h - rowsum at rows 4 l .. 4 l + 3, lane l >= 32 takes h
+// at rows 4 (l - 32) .. 4 (l - 32) + 3.
 __device__ __forceinline__ v4i fetch_rows(const DeviceProblem& prob, int tile) {
     int ln = threadIdx.x & 63;
     asm volatile("" : "+v"(ln));
-    return *reinterpret_cast<const v4i*>((ln < 32 ? prob.hr : (kFp4 ? prob.h : prob.er)) + tile * kTileRows +
-                                         4 * (ln & 31));
+    return *reinterpret_cast<const v4i*>((ln < 32 ? prob.hr : prob.h) + tile * kTileRows + 4 * (ln & 31));
 }
 
 // Writes the row vectors fetched by this lane into the wave's staging area, each plus its cycle constant.
@@ -258,10 +257,6 @@ __device__ __forceinline__ int agpr_read(int x) {
     return r;
 }
 
-// Twice the field part of the counter input, 2 sum_j J_ij x_j, plus the accumulator's constant offset.
-template <bool kFp4>
-__device__ __forceinline__ int field2(int acc) { return kFp4 ? acc : acc * 2; }
-
 // Fused epilogue of one 128-row tile for the kNBF column fragments of this wave.  Lane (column
 // 16 f + (lane & 15), group g = lane >> 4) owns tile rows 32 g .. 32 g + 31 of fragment f, i.e. one 32-bit
 // word of every bit plane and of the Philox block, and 32 consecutive int8 counters.  With kUpdate the
@@ -319,8 +314,6 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
             const v4i er4 = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
-            v4i hq4 = v4i{0, 0, 0, 0};   // fp4: already in the accumulator
-            if (kUpdate && !kFp4) hq4 = *reinterpret_cast<const v4i*>(x.rows + 32 * eg + 4 * ai);
             uint32_t isw_new = 0;
             int nvs[4] = {0, 0, 0, 0};
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
@@ -335,11 +328,12 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int pos = 8 * j + ai;
-                const int f2 = field2<kFp4>(kNBF == 8 ? agpr_read(acc[ai][f][j]) : acc[ai][f][j]);
+                // the counter input without Is and the noise and coupling bytes (plus 0x4B400000 with fp4)
+                const int f2 = kNBF == 8 ? agpr_read(acc[ai][f][j]) : acc[ai][f][j];
                 // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
                 ep4[j] = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep4[j]);
                 if (kUpdate) {
-                    const int base = kFp4 ? f2 : f2 + hq4[j];
+                    const int base = f2;
                     int nv;
                     if (kFast) {
                         nv = med3_i32(base + (int)bfe_u(s4, 8 * j, 8), lo, hi);
@@ -594,7 +588,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     const BlockLds L{planes, npl, plane_words, cstride, e_acc, hit_l, best_l, colinfo};
     block_init<kNB>(a, wg, L);
 
-    const int P = a.prob.planes;
+    // 128-column blocks with int8 operands take single-plane problems only (the host checks it): a Horner
+    // update of 256 AGPR accumulators would need more VGPRs than are left beside them.
+    const int P = (kNBF == 8 && !kFp4) ? 1 : a.prob.planes;
     // Buffer resource over all J planes (gfx9 raw buffer, byte addressed).
     const __amdgpu_buffer_rsrc_t jrsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(a.prob.J), 0, P * np * np, 0x00020000);
@@ -613,8 +609,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         //   s = Is + 2 sum_j J_ij x_j + (h - rowsum) - n_rnd - q (1 + mode) + 2 n_rnd [r = +1]
         //       + 2 q [sigma_up = +1] (+ 2 q [sigma_dn = +1] in mode 1).
         // The fast path writes q (2 [sigma = +1] - 1) as 2 |q| [sigma = sign q] - |q|.
-        // With fp4 operands the accumulator is an fp32 number 1.5 * 2^23 + v with v an integer below 2^22 in
-        // magnitude, whose bits are kAccOffset + v; the epilogue works on those bits directly.
+        // The accumulator starts from the per-row part of s and collects 2 sum_j J_ij x_j, so that it ends as
+        // v = s - Is - (the noise and coupling increments).  With fp4 operands it is an fp32 number 1.5 * 2^23 + v
+        // with v an integer below 2^22 in magnitude, whose bits are kAccOffset + v; the epilogue works on those
+        // bits directly.  With int8 operands it is v itself (int32).
         constexpr int kAccOffset = kFp4 ? 0x4B400000 : 0;
         const int qa = kFast ? (q < 0 ? -q : q) : q;
         const int two_n = 2 * a.noise_amp;
@@ -623,9 +621,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         // The fast path adds the counters offset by 128, which the per-row constant takes back.
         const int adj_c = adj - (kFast ? 128 : 0);
         // Per-row constants staged with each tile (see the tile loop): the first vector (h - rowsum) gets
-        // row_add_h, the second (h for fp4, 2 h - rowsum for int8) gets row_add_e.
+        // row_add_h, the second (h) gets row_add_e.
         const int row_add_h = adj_c + kAccOffset;
-        const int row_add_e = kFp4 ? -adj_c - kAccOffset : 0;
+        const int row_add_e = -adj_c - kAccOffset;
         const uint32_t qflip = (kFast && q < 0) ? 0xFFFFFFFFu : 0u;
         const uint32_t* pl_cur = planes + p_cur * plane_words;
         const uint32_t* pl_del = planes + p_del * plane_words;
@@ -636,10 +634,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         v4i rowv_next;
         auto tile_body = [&](auto kF_c, const int tile, const int foff, const bool more, const int next_tile) {
             constexpr int kF = decltype(kF_c)::value;
-            // Per-row constants of this tile, staged in LDS for the first K step and the epilogue:
-            //   fp4:  [0, 128) the accumulator's start, 0x4B400000 + h - rowsum + row_add_h (as fp32 bits),
-            //         [128, 256) h - row_add_h - 0x4B400000, so that start + 2 field + this = 2 h + F;
-            //   int8: [0, 128) h - rowsum + row_add_h, [128, 256) 2 h - rowsum.
+            // Per-row constants of this tile, staged in LDS for the first K step and the epilogue: [0, 128) the
+            // accumulator's start, kAccOffset + h - rowsum + adj_c (fp32 bits with fp4 operands), [128, 256)
+            // h - adj_c - kAccOffset, so that start + 2 sum_j J_ij x_j + this = 2 h + F (the energy term).
             stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
             const int32_t* rows_w = rowst + wave * 256;
             v4i acc[8][kF];
@@ -711,7 +708,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                 // are fetched instead.
                 read_words(wn, ns - 1);
                 mma_fp4_cols<kF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
-                if (more) rowv_next = fetch_rows<kFp4>(a.prob, next_tile);
+                if (more) rowv_next = fetch_rows(a.prob, next_tile);
                 prefetch_counters<kF, kFp4>(cnt, is_lane, np);
                 mma_fp4_cols<kF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
 #pragma unroll
@@ -720,7 +717,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                     for (int f = 0; f < kF; ++f) acc[ai][f] = __builtin_bit_cast(v4i, accf[ai][f]);
             } else {
                 // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
-                // group g ends up with rows 32 g .. 32 g + 31.
+                // group g ends up with rows 32 g .. 32 g + 31.  The operand is 2 x, so the accumulators collect
+                // 2 sum_j J_ij x_j on top of the staged start (the counter input v, as with fp4 operands).
                 const uint32_t* bsrc = pl_cur + (tcol + 16 * foff) * cstride + (tg >> 1);
                 const int bsh = 4 * (tg & 1);
                 // Bit-plane words of two consecutive K steps, used alternately (w: even steps, wn: odd steps).
@@ -729,16 +727,25 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
 #pragma unroll
                     for (int f = 0; f < kF; ++f) dst[f] = bsrc[16 * f * cstride + 2 * s];
                 };
+                // The accumulators start from the staged constants (for a single plane; zero when several planes
+                // follow), and each later pass scales the running sum by 256 (exact Horner evaluation over the
+                // planes), the last one adding the start.  Setting them takes the moves a zero start took before.
 #pragma unroll
-                for (int ai = 0; ai < 8; ++ai)
+                for (int ai = 0; ai < 8; ++ai) {
+                    v4i st = *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai);
+                    if (P != 1) st = v4i{0, 0, 0, 0};
 #pragma unroll
-                    for (int f = 0; f < kF; ++f) acc[ai][f] = v4i{0, 0, 0, 0};
+                    for (int f = 0; f < kF; ++f) acc[ai][f] = st;
+                }
                 for (int p = P - 1; p >= 0; --p) {
-                    if (p < P - 1) {
+                    if (p < P - 1) {   // never with 128 columns (P = 1 there)
 #pragma unroll
-                        for (int ai = 0; ai < 8; ++ai)
+                        for (int ai = 0; ai < 8; ++ai) {
+                            v4i st = *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai);
+                            if (p != 0) st = v4i{0, 0, 0, 0};
 #pragma unroll
-                            for (int f = 0; f < kF; ++f) acc[ai][f] = acc[ai][f] * 256;
+                            for (int f = 0; f < kF; ++f) acc[ai][f] = acc[ai][f] * 256 + st;
+                        }
                     }
                     // J is read through a buffer resource (loads past the planes return 0 instead of faulting),
                     // one contiguous 1 KiB fragment per load, into two A buffers: buffer b holds step s while the
@@ -752,7 +759,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                     // the previous steps issued in fragment order, so each MFMA group waits for its own fragment.
                     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
                     v4i Bc = expand_operand(w[0] >> bsh);
-                    for (int s = 0; s < nsteps - 2; s += 2) {
+                    int s = 0;
+                    for (; s < nsteps - 2; s += 2) {
                         read_words(wn, s + 1);
                         mma_i8_cols<kF, true, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
                         read_words(w, s + 2);
@@ -762,7 +770,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
                     read_words(wn, nsteps - 1);
                     mma_i8_cols<kF, false, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, 0);
                     if (p == 0) {
-                        if (more) rowv_next = fetch_rows<kFp4>(a.prob, next_tile);
+                        if (more) rowv_next = fetch_rows(a.prob, next_tile);
                         prefetch_counters<kF, kFp4>(cnt, is_lane, np);
                     }
                     mma_i8_cols<kF, false, false>(A1, Bc, wn, 0u, bsh, acc, jrsrc, voff, 0);
@@ -813,7 +821,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         // or two tiles over, those are split into column halves (4 fragments, all 128 rows each), one per wave,
         // so that the last round is shared instead of leaving two or three waves (one per SIMD) idle.  Narrower
         // blocks keep the plain loop (two workgroups per CU fill each other's idle waves).
-        constexpr bool kCanSplit = kFp4 && kNBF == 8;
+        constexpr bool kCanSplit = kNBF == 8;
         if constexpr (kCanSplit) {
             const int rounds = ntiles / kWaves, left = ntiles % kWaves;
             const bool split = left == 1 || left == 2;
@@ -823,7 +831,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
             // Row vectors of the wave's first tile; later tiles' are fetched during the previous tile's last K
             // steps.  A wave without work fetches the last tile's instead, so that the load stays inside the row
             // vectors.
-            rowv_next = fetch_rows<kFp4>(a.prob, n_full > 0 ? wave : has_half ? half_tile : ntiles - 1);
+            rowv_next = fetch_rows(a.prob, n_full > 0 ? wave : has_half ? half_tile : ntiles - 1);
             for (int i = 0; i < n_full; ++i) {
                 const int tile = wave + kWaves * i;
                 const bool last_full = i + 1 == n_full;
@@ -834,7 +842,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         } else {
             // A wave without a tile (fewer tiles than waves) fetches the last tile's row vectors instead, so that
             // the load stays inside the row vectors; it never uses them.
-            rowv_next = fetch_rows<kFp4>(a.prob, wave < ntiles ? wave : ntiles - 1);
+            rowv_next = fetch_rows(a.prob, wave < ntiles ? wave : ntiles - 1);
             for (int tile = wave; tile < ntiles; tile += kWaves)
                 tile_body(std::integral_constant<int, kNBF>{}, tile, 0, tile + kWaves < ntiles, tile + kWaves);
         }
@@ -1066,13 +1074,15 @@ hipError_t configure_variant() {
 }
 
 // Variant v < 16: bit 3 fast epilogue, bit 2 coupling mode 1, bit 1 fp4 operands, bit 0 32 columns per
-// workgroup (else 64).  v = 16 .. 19: 128 columns, fp4 operands; bit 1 fast epilogue, bit 0 coupling mode 1.
+// workgroup (else 64).  v = 16 .. 23: 128 columns; v = 16 .. 19 fp4 operands, 20 .. 23 int8 operands; bit 1
+// fast epilogue, bit 0 coupling mode 1.
 #define SSQA_FOR_EACH_VARIANT(X) \
     X(0, false, 0, 4, false) X(1, false, 0, 2, false) X(2, false, 0, 4, true) X(3, false, 0, 2, true) \
     X(4, false, 1, 4, false) X(5, false, 1, 2, false) X(6, false, 1, 4, true) X(7, false, 1, 2, true) \
     X(8, true, 0, 4, false) X(9, true, 0, 2, false) X(10, true, 0, 4, true) X(11, true, 0, 2, true) \
     X(12, true, 1, 4, false) X(13, true, 1, 2, false) X(14, true, 1, 4, true) X(15, true, 1, 2, true) \
-    X(16, false, 0, 8, true) X(17, false, 1, 8, true) X(18, true, 0, 8, true) X(19, true, 1, 8, true)
+    X(16, false, 0, 8, true) X(17, false, 1, 8, true) X(18, true, 0, 8, true) X(19, true, 1, 8, true) \
+    X(20, false, 0, 8, false) X(21, false, 1, 8, false) X(22, true, 0, 8, false) X(23, true, 1, 8, false)
 
 hipError_t configure_sweep_kernels() {
     static hipError_t status = [] {
@@ -1087,7 +1097,7 @@ hipError_t configure_sweep_kernels() {
 }
 
 int sweep_variant(bool fast, int mode, int nb, bool fp4) {
-    if (nb == 128) return fp4 ? 16 + (fast ? 2 : 0) + (mode ? 1 : 0) : -1;
+    if (nb == 128) return (fp4 ? 16 : 20) + (fast ? 2 : 0) + (mode ? 1 : 0);
     return (fast ? 8 : 0) + (mode ? 4 : 0) + (fp4 ? 2 : 0) + (nb == 32 ? 1 : 0);
 }
 

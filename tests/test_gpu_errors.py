@@ -76,7 +76,8 @@ CASES = [
 def problems(lib):
     h, J, e_star = gi_case(5, 0)                      # N = 25, every J entry exact in fp4
     hi, Ji = random_ising(40, 2, h_max=30, j_max=11)  # entries such as 5 and 7: int8 operands only
-    return (lib.Problem(h, J), h, J, e_star), lib.Problem(hi, Ji)
+    hp, Jp = random_ising(40, 3, h_max=30, j_max=500)  # |J| beyond 127: two int8 planes
+    return (lib.Problem(h, J), h, J, e_star), lib.Problem(hi, Ji), lib.Problem(hp, Jp)
 
 
 @pytest.mark.parametrize("name,change,status,text", CASES, ids=[c[0] for c in CASES])
@@ -91,13 +92,19 @@ def test_anneal_rejects(lib, problems, name, change, status, text):
 
 
 def test_fp4_only_requests_on_int8_problem(lib, problems):
+    """fp4 operands on a J without fp4 codes are refused; 128 columns with int8 operands are refused only
+    when J needs more than one int8 plane."""
     _note("case fp4-only requests on an int8 problem")
     prob = problems[1]
-    assert not prob.fp4_exact
-    for change, text in ((dict(operand_format=2), "fp4"), (dict(block_columns=128), "fp4")):
-        with pytest.raises(lib.SSQAError) as ei:
-            lib.ssqa_anneal(prob, **dict(_base(), **change))
-        assert ei.value.name == "SSQA_ENOTSUP" and text in str(ei.value), str(ei.value)
+    assert not prob.fp4_exact and prob.planes == 1
+    with pytest.raises(lib.SSQAError) as ei:
+        lib.ssqa_anneal(prob, **dict(_base(), operand_format=2))
+    assert ei.value.name == "SSQA_ENOTSUP" and "fp4" in str(ei.value), str(ei.value)
+    two = problems[2]
+    assert two.planes == 2
+    with pytest.raises(lib.SSQAError) as ei:
+        lib.ssqa_anneal(two, **dict(_base(), block_columns=128))
+    assert ei.value.name == "SSQA_ENOTSUP" and "one int8 plane" in str(ei.value), str(ei.value)
 
 
 def test_batch_rejects_a_bad_job(lib, problems):

@@ -239,9 +239,39 @@ def test_wide_blocks_fp4(lib, n, R, T, SC, delay, mode, fast):
     assert_same(wide, run_oracle(h, J, **kw))
 
 
-def test_wide_blocks_need_fp4(lib):
-    h, J = random_ising(100, 5, h_max=10, j_max=9)          # entries of 5, 7, 8, 9 have no fp4 code
+@pytest.mark.parametrize("n,R,T,SC,delay,mode,fast,j_max", [
+    (300, 16, 20, 30, 1, 0, True, 9),      # byte-parallel epilogue, entries without fp4 codes, ragged tiles
+    (700, 64, 5, 20, 2, 1, False, 127),    # general epilogue, |J| up to 127, both ring neighbours, d = 2
+    (129, 1, 200, 15, 0, 0, True, 60),     # 128 single-replica trials per block, one row past a tile
+    (100, 8, 20, 10, 1, 0, True, 50),      # one tile of two K steps, split into column halves
+    (200, 128, 3, 12, 1, 1, True, 11),     # R = 128: one trial fills a block
+    (600, 32, 9, 14, 1, 0, True, 100),     # 5 tiles: one round of four waves, then one tile left over (split)
+    (1100, 16, 8, 8, 1, 1, False, 127),    # 9 tiles: two rounds, one left over, general epilogue
+    (880, 32, 6, 12, 1, 0, True, 33),      # 7 tiles: one round, then three left over
+])
+def test_wide_blocks_int8(lib, n, R, T, SC, delay, mode, fast, j_max):
+    """128 columns per workgroup with int8 operands (2 x in {0, 2} against one int8 plane, int32 accumulators
+    starting from the per-row constants, in the AGPRs) equal the 64-column tiling and the oracle bit for bit."""
+    _note(f"case 128-column int8 blocks n={n} R={R} T={T} d={delay} mode={mode} |J|<={j_max}")
+    h, J = random_ising(n, n + 5 * R, h_max=90, j_max=j_max)
+    rng = np.random.default_rng(n + R + 1)
+    q = rng.integers(-6, 7, size=SC)
+    i0 = rng.integers(8, 30, size=SC) if fast else rng.integers(5, 100, size=SC)
     prob = lib.Problem(h, J)
+    assert prob.planes == 1
+    kw = dict(replicas=R, trials=T, cycles=SC, q=q, i0=i0, alpha=1, noise=9, delay=delay, seed=n, mode=mode)
+    wide = run_gpu(prob, block_columns=128, operand_format=1, **kw)
+    if R <= 64:
+        ref64 = run_gpu(prob, block_columns=64, operand_format=1, **kw)
+        for key in ("best", "first_hit", "trace", "Is"):
+            assert np.array_equal(wide[key], ref64[key]), key
+    assert_same(wide, run_oracle(h, J, **kw))
+
+
+def test_wide_int8_blocks_need_one_plane(lib):
+    h, J = random_ising(100, 5, h_max=10, j_max=300)        # |J| beyond 127: two int8 planes
+    prob = lib.Problem(h, J)
+    assert prob.planes == 2
     with pytest.raises(lib.SSQAError) as ei:
         lib.ssqa_anneal(prob, replicas=4, trials=2, cycles=3, jperp=np.zeros(3, np.int32), i0=np.full(3, 20),
                         alpha=1, noise_amp=4, delay=1, seed=0, block_columns=128)
@@ -267,7 +297,7 @@ def test_large_n_uses_narrow_blocks(lib):
 @pytest.mark.parametrize("n,block_columns,formats", [
     (13056, 0, (2, 1)),     # 32-column blocks (chosen by themselves), fp4 and int8 operands
     (6400, 64, (2, 1)),     # 64-column blocks
-    (3072, 128, (2,)),      # 128-column blocks (fp4 only), 24 tiles
+    (3072, 128, (2, 1)),    # 128-column blocks, 24 tiles
 ])
 def test_maximum_n_at_the_lds_limit(lib, n, block_columns, formats):
     """The largest padded size whose bit planes fit in LDS for each block width at d = 1 (the workgroup's

@@ -98,10 +98,17 @@ def test_set_refuses_an_illegal_tile(lib):
         lib.ssqa_tune_set(prob, {"block_columns": 32, "trials_per_block": 1, "operands": "int8"}, **kw)
     assert err.value.name == "SSQA_ENOTSUP"
     with pytest.raises(lib.SSQAError):
-        lib.ssqa_tune_set(prob, {"block_columns": 128, "trials_per_block": 1, "operands": "int8"}, **kw)
-    with pytest.raises(lib.SSQAError):
         lib.ssqa_tune_anneal(prob, block_columns=64, **kw)
+    # 128 columns with int8 operands need J in one int8 plane
+    h2, J2 = random_ising(100, 9, h_max=50, j_max=300)
+    two = lib.Problem(h2, J2)
+    assert two.planes == 2
+    kw2 = dict(kw, replicas=8)
+    with pytest.raises(lib.SSQAError):
+        lib.ssqa_tune_set(two, {"block_columns": 128, "trials_per_block": 1, "operands": "int8"}, **kw2)
+    lib.ssqa_tune_set(prob, {"block_columns": 128, "trials_per_block": 1, "operands": "int8"}, **kw2)
     prob.close()
+    two.close()
 
 
 def test_tuned_batch_equals_plain(lib):
