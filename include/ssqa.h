@@ -296,6 +296,10 @@ typedef struct ssqa_server_config {
     int32_t cycles_per_step;   /* K >= 1: cycles every active request advances per step          */
     int32_t max_active;        /* at most this many requests on the device at once (1..65535)    */
     int64_t memory_budget;     /* bytes of device memory admitted requests may hold together     */
+    int32_t split_rows;        /* a request whose N pads to at least this many rows (and whose block
+                                  is narrower than 128 columns) spreads each trial's rows over row
+                                  groups of workgroups, one launch per cycle (Section 3.2's parallel
+                                  update of all N R spins over more of the chip); 0 = 4096, -1 = never */
 } ssqa_server_config;
 
 typedef struct ssqa_request {

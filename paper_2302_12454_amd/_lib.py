@@ -79,6 +79,7 @@ class ServerConfig(ctypes.Structure):
         ("cycles_per_step", ctypes.c_int32),
         ("max_active", ctypes.c_int32),
         ("memory_budget", ctypes.c_int64),
+        ("split_rows", ctypes.c_int32),
     ]
 
 

@@ -493,9 +493,10 @@ class Server:
     """ssqa_server_*: continuous batching of anneal requests with memory-based admission."""
 
     def __init__(self, device: int = 0, cycles_per_step: int = 100, max_active: int = 64,
-                 memory_budget: int = 64 << 30):
+                 memory_budget: int = 64 << 30, split_rows: int = 0):
         lib = _lib.load()
-        cfg = _lib.ServerConfig(int(device), int(cycles_per_step), int(max_active), int(memory_budget))
+        cfg = _lib.ServerConfig(int(device), int(cycles_per_step), int(max_active), int(memory_budget),
+                                int(split_rows))
         handle = ctypes.c_void_p()
         _check(lib.ssqa_server_create(ctypes.byref(cfg), ctypes.byref(handle)), "ssqa_server_create")
         self._handle = handle

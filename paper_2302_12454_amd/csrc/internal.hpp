@@ -91,7 +91,21 @@ struct SweepArgs {
     int64_t* best;          // [T]
     int32_t* first_hit;     // [T]
     int32_t* trace;         // [(SC + 1)][T * R] or nullptr; row t holds cycle t
+    // Row-split form (sweep_split_kernel): one launch per cycle over n_cb column blocks (is_state as above, block
+    // index in place of the workgroup) times n_groups row groups of group_tiles row tiles; sigma's bit-plane ring
+    // and the per-column energy sums live in device memory between launches.
+    int32_t n_groups;       // row groups per column block
+    int32_t group_tiles;    // row tiles per group
+    int32_t n_cb;           // column blocks
+    uint32_t* ring;         // [d + 2][n_cb][nb][np / 32]: sigma(t) in ring slot t % (d + 2), spread bit order
+    int32_t* e_sum;         // [2][n_cb * nb]: sum_i sigma_i (2 h_i + F_i) of cycle t in slot t & 1
 };
+
+// Flags of one sweep_split_kernel launch at cycle t.
+constexpr int kSplitInit = 1;    // sigma(0) and Is(0) of the group's rows, best and first hit reset (t = 0)
+constexpr int kSplitClose = 2;   // first reduce cycle t - 1's energies to the trace, best and first hit
+constexpr int kSplitRun = 4;     // then the field product, energy and (with kSplitUpdate) the update of cycle t
+constexpr int kSplitUpdate = 8;
 
 // Launchers (sweep.hip).  Return hipSuccess or the launch error.
 // rowvec receives [h | hr | er], three int32 vectors of np entries.
@@ -109,6 +123,9 @@ int sweep_variant(bool fast, int mode, int nb, bool fp4);
 // Columns per workgroup of a variant.
 int variant_columns(int variant);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
+// One launch of the row-split sweep (item: device copy of the anneal's arguments; grid n_cb * n_groups; kSplit*
+// flags) for a variant with 32 or 64 columns per workgroup.
+hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int t, int flags, hipStream_t stream);
 // items: device array of anneals; work: device list of (item << 16 | column block), n_work entries, all of
 // one kernel variant; the LDS size is taken for the largest padded N and delay among them.
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,

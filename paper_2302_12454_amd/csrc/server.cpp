@@ -8,6 +8,12 @@
 // exit) or their last cycle, releasing their memory.  A request's results depend only on its own inputs:
 // the random stream is keyed by its seed and its own cycle counter, and retirement is decided at its own
 // cycle boundaries, so a request gives the same result alone or among others.
+//
+// A request of large N would otherwise run on few workgroups (one per block of whole trials), each reading all
+// of J every cycle.  From `split_rows` padded rows on it takes the row-split form instead: every block of
+// trials is spread over row groups of workgroups, one launch per cycle on a second stream beside the
+// persistent launch of the other requests, with sigma exchanged through device memory and the kernel boundary
+// as the per-cycle barrier.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,6 +51,8 @@ struct Request {
     void* mem = nullptr;                 // schedules | counters | history | best | first_hit
     int64_t bytes = 0;
     int nb = 64, n_wg = 0;
+    bool split = false;                  // row-split form (args.n_groups row groups per block of trials)
+    SweepArgs* d_args = nullptr;         // device copy of args (split form)
     SweepArgs args{};
     int cycle = 0;
     // results
@@ -63,15 +71,33 @@ int64_t request_blocks(int n, const ssqa_anneal_params& pa) {
     return (pa.trials + tpw - 1) / tpw;
 }
 
+// Padded rows from which a request takes the row-split form (0 in the configuration: 4096; -1: never).
+int split_floor(int split_rows) { return split_rows == 0 ? 4096 : split_rows < 0 ? INT32_MAX : split_rows; }
+
+// Whether a request takes the row-split form: enough rows, and a block narrower than 128 columns.
+bool takes_split(int np, int nb, int split_rows) { return np >= split_floor(split_rows) && nb <= 64; }
+
+// Row tiles per group of the row-split form (one per wave), and the groups of a block: enough to cover the
+// tiles, rounded up to a multiple of the XCD count so that a row group's copies in every block share an XCD.
+constexpr int kGroupTiles = 4;
+int split_groups(int np, int xcds) {
+    const int g = (np / kTileRows + kGroupTiles - 1) / kGroupTiles;
+    return (g + xcds - 1) / xcds * xcds;
+}
+
 // Device bytes of one admitted request: int8 planes, the fp4 copy of J (counted whether or not the
-// problem turns out to be fp4-exact), row vectors, counters, bit-plane history, outputs, schedules.
-int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa) {
+// problem turns out to be fp4-exact), row vectors, counters, bit-plane history (or, in the row-split form,
+// the bit-plane ring and energy sums), outputs, schedules.
+int64_t request_bytes(int n, int planes_hint, const ssqa_anneal_params& pa, int split_rows) {
     const int64_t np = padded_rows(n);
     const int64_t kp4 = fp4_k_extent((int)np);
     const int64_t nb = block_columns_for((int)np, &pa);
     const int64_t n_wg = request_blocks(n, pa);
-    return planes_hint * np * np + np * kp4 / 2 + 12 * np + n_wg * nb * np +
-           n_wg * std::max(pa.delay, 1) * nb * np / 8 + 12LL * pa.trials + 8LL * std::max(pa.cycles, 1) + 1024;
+    const int64_t state = takes_split((int)np, (int)nb, split_rows)
+                              ? (pa.delay + 2LL) * n_wg * nb * np / 8 + 8 * n_wg * nb + (int64_t)sizeof(SweepArgs)
+                              : n_wg * std::max(pa.delay, 1) * nb * np / 8;
+    return planes_hint * np * np + np * kp4 / 2 + 12 * np + n_wg * nb * np + state + 12LL * pa.trials +
+           8LL * std::max(pa.cycles, 1) + 4096;
 }
 
 }  // namespace
@@ -91,6 +117,10 @@ struct ssqa_server {
     std::vector<uint32_t> work;
     int64_t cycles_run = 0;
     double spin_updates = 0;
+    // second stream of the row-split requests' launches, and the events that fork it from and join it to the
+    // caller's stream (created at the first split request)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -117,14 +147,24 @@ ssqa_status admit(ssqa_server* s, Request* r) {
     r->n_wg = (pa.trials + tpw - 1) / tpw;
     if (r->n_wg > 65535) return fail(SSQA_EINVAL, "request needs %d workgroups (> 65535)", r->n_wg);
     const int np = r->prob->dev.np;
+    r->split = takes_split(np, r->nb, s->cfg.split_rows);
+    const int n_groups = r->split ? split_groups(np, device_xcd_count(s->cfg.device)) : 0;
+    if (r->split && (int64_t)n_groups * r->n_wg > (1LL << 30))
+        return fail(SSQA_EINVAL, "request needs too many row-split workgroups");
     const int SC = std::max(pa.cycles, 1);
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t o_sched = 0;
-    const size_t o_is = (size_t)(2 * SC * 4 + 255) / 256 * 256;
+    const size_t o_is = align((size_t)2 * SC * 4);
     const size_t is_bytes = (size_t)r->n_wg * r->nb * np;
-    const size_t o_hist = o_is + (is_bytes + 255) / 256 * 256;
-    const size_t hist_bytes = (size_t)r->n_wg * std::max(pa.delay, 1) * r->nb * (np / 32) * 4;
-    const size_t o_best = o_hist + (hist_bytes + 255) / 256 * 256;
-    const size_t o_hit = o_best + ((size_t)pa.trials * 8 + 255) / 256 * 256;
+    const size_t o_hist = o_is + align(is_bytes);
+    // history for the persistent form; the ring of d + 2 planes and two energy slots for the row-split form
+    const size_t hist_bytes = r->split ? (size_t)(pa.delay + 2) * r->n_wg * r->nb * (np / 32) * 4
+                                       : (size_t)r->n_wg * std::max(pa.delay, 1) * r->nb * (np / 32) * 4;
+    const size_t o_esum = o_hist + align(hist_bytes);
+    const size_t esum_bytes = r->split ? (size_t)2 * r->n_wg * r->nb * 4 : 0;
+    const size_t o_item = o_esum + align(esum_bytes);
+    const size_t o_best = o_item + align(r->split ? sizeof(SweepArgs) : 0);
+    const size_t o_hit = o_best + align((size_t)pa.trials * 8);
     const size_t total = o_hit + (size_t)pa.trials * 4;
     DeviceGuard guard(s->cfg.device);
     if (hipMalloc(&r->mem, total) != hipSuccess) return fail(SSQA_ENOMEM, "device allocation of %zu bytes failed", total);
@@ -140,6 +180,20 @@ ssqa_status admit(ssqa_server* s, Request* r) {
                                    nullptr, nullptr};
     r->args = make_args(r->prob, &pa, &outs, d_jperp, d_i0, reinterpret_cast<int8_t*>(base + o_is),
                         reinterpret_cast<uint32_t*>(base + o_hist));
+    if (r->split) {
+        SweepArgs& a = r->args;
+        a.hist_state = nullptr;
+        a.n_cb = r->n_wg;
+        a.n_groups = n_groups;
+        a.group_tiles = kGroupTiles;
+        a.ring = reinterpret_cast<uint32_t*>(base + o_hist);
+        a.e_sum = reinterpret_cast<int32_t*>(base + o_esum);
+        r->d_args = reinterpret_cast<SweepArgs*>(base + o_item);
+        // the energy slots start at zero (each close clears the slot it read); the arguments never change
+        if (hipMemset(a.e_sum, 0, esum_bytes) != hipSuccess ||
+            hipMemcpy(r->d_args, &a, sizeof(SweepArgs), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(SSQA_EDEVICE, "row-split state upload failed");
+    }
     r->bytes = (int64_t)total + (int64_t)r->prob->dev.planes * np * np + 12LL * np;
     r->cycle = 0;
     r->best.assign(pa.trials, INT64_MAX);
@@ -233,7 +287,7 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
             s->queue.pop_front();
             continue;
         }
-        const int64_t need = request_bytes(r->n, r->planes, r->params);
+        const int64_t need = request_bytes(r->n, r->planes, r->params, s->cfg.split_rows);
         if (need > s->cfg.memory_budget) {          // can never fit: refuse it
             s->queue.pop_front();
             r->state = SSQA_REQ_FAILED;
@@ -280,6 +334,7 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
     int max_np[kVariants] = {}, max_delay[kVariants] = {};
     s->items.resize(n);
     double updates = 0;
+    bool any_split = false;
     for (int i = 0; i < n; ++i) {
         Request* r = s->active[i];
         SweepArgs a = r->args;
@@ -289,6 +344,10 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
         a.save_hist = a.final_pass ? 0 : 1;
         s->items[i] = a;
         updates += (double)r->n * r->params.replicas * r->params.trials * (a.t_end - a.t_begin);
+        if (r->split) {
+            any_split = true;
+            continue;
+        }
         const int v = sweep_variant(a.fast != 0, a.mode, a.nb, a.fp4 != 0);
         const double np = a.prob.np;
         const double cost = np * np * a.prob.planes * (a.t_end - a.t_begin + 1);
@@ -322,12 +381,44 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
     auto* d_work = reinterpret_cast<uint32_t*>(static_cast<char*>(s->table) + (sizeof(SweepArgs) * n + 255) / 256 * 256);
     SSQA_HIP(configure_sweep_kernels(), "configure");
     SSQA_HIP(hipMemcpyAsync(d_items, s->items.data(), sizeof(SweepArgs) * n, hipMemcpyHostToDevice, stream), "upload");
-    SSQA_HIP(hipMemcpyAsync(d_work, s->work.data(), sizeof(uint32_t) * s->work.size(), hipMemcpyHostToDevice, stream),
-             "upload");
+    if (!s->work.empty())
+        SSQA_HIP(hipMemcpyAsync(d_work, s->work.data(), sizeof(uint32_t) * s->work.size(), hipMemcpyHostToDevice,
+                                stream), "upload");
+    // Row-split requests: their K cycles as one launch per cycle on the second stream, beside the persistent
+    // launches below.  Launch t closes cycle t - 1 (except the step's first) and runs cycle t; a last launch
+    // closes the step's last cycle, so that best energies and first hits are current at the readback.
+    if (any_split) {
+        if (!s->side) {
+            SSQA_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking), "side stream");
+            SSQA_HIP(hipEventCreateWithFlags(&s->fork, hipEventDisableTiming), "event");
+            SSQA_HIP(hipEventCreateWithFlags(&s->join, hipEventDisableTiming), "event");
+        }
+        SSQA_HIP(hipEventRecord(s->fork, stream), "fork");
+        SSQA_HIP(hipStreamWaitEvent(s->side, s->fork, 0), "fork");
+        for (int i = 0; i < n; ++i) {
+            Request* r = s->active[i];
+            if (!r->split) continue;
+            const SweepArgs& a = s->items[i];
+            const int c0 = a.t_begin, c1 = a.t_end;
+            if (c0 == 0) SSQA_HIP(launch_sweep_split(r->d_args, a, 0, kSplitInit, s->side), "split init");
+            for (int t = c0; t < c1; ++t)
+                SSQA_HIP(launch_sweep_split(r->d_args, a, t, kSplitRun | kSplitUpdate | (t > c0 ? kSplitClose : 0),
+                                            s->side), "split cycle");
+            int last = c1 - 1;
+            if (a.final_pass) {   // the energy of sigma(SC)
+                SSQA_HIP(launch_sweep_split(r->d_args, a, c1, kSplitRun | (c1 > c0 ? kSplitClose : 0), s->side),
+                         "split final");
+                last = c1;
+            }
+            if (last >= c0) SSQA_HIP(launch_sweep_split(r->d_args, a, last + 1, kSplitClose, s->side), "split close");
+        }
+        SSQA_HIP(hipEventRecord(s->join, s->side), "join");
+    }
     for (int v = 0; v < kVariants; ++v) {
         if (!len[v]) continue;
         SSQA_HIP(launch_sweep_batch(d_items, d_work + off[v], (int)len[v], max_np[v], max_delay[v], v, stream), "step");
     }
+    if (any_split) SSQA_HIP(hipStreamWaitEvent(stream, s->join, 0), "join");
     // 3. read back and retire at the requests' own cycle boundaries
     for (int i = 0; i < n; ++i) {
         Request* r = s->active[i];
@@ -410,8 +501,12 @@ ssqa_status ssqa_server_stats(ssqa_server_t s, ssqa_server_stats_t* out) {
 void ssqa_server_destroy(ssqa_server_t s) {
     if (!s) return;
     DeviceGuard guard(s->cfg.device);
+    if (s->side) (void)hipStreamSynchronize(s->side);
     for (auto& kv : s->all) release_device(kv.second.get());
     if (s->table) (void)hipFree(s->table);
+    if (s->fork) (void)hipEventDestroy(s->fork);
+    if (s->join) (void)hipEventDestroy(s->join);
+    if (s->side) (void)hipStreamDestroy(s->side);
     delete s;
 }
 

@@ -552,6 +552,168 @@ __device__ __forceinline__ void block_close(const SweepArgs& a, const int wg, co
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Row-split form: a trial's rows are spread over the row groups of its column block, one launch per cycle.
+// ---------------------------------------------------------------------------------------------
+
+// Row tiles [lo, hi) of row group g.
+struct TileRange {
+    int lo, hi;
+};
+__device__ __forceinline__ TileRange group_tiles(const SweepArgs& a, int g) {
+    const int ntiles = a.prob.np / kTileRows;
+    const int lo = min(g * a.group_tiles, ntiles);
+    return TileRange{lo, min(lo + a.group_tiles, ntiles)};
+}
+
+// sigma(0) and Is(0) of group g's rows of column block cb from the random stream (tag 0), into the ring slots
+// of sigma(0) and sigma(-s), s = 1..d; group 0 also resets the block's best energies and first hits.
+template <int kNB>
+__device__ void split_init_state(const SweepArgs& a, const int cb, const int g) {
+    const int np = a.prob.np, words = np / 32, npl = a.delay + 2;
+    const int R = a.R, b0 = cb * a.tpw;
+    const TileRange tr = group_tiles(a, g);
+    int8_t* is_wg = a.is_state + (size_t)cb * kNB * np;
+    for (int u = threadIdx.x; u < (tr.hi - tr.lo) * kNB; u += kThreads) {
+        const int tile = tr.lo + u / kNB;
+        const int c = u % kNB;
+        const int k = c % R;
+        const int b = b0 + c / R;
+        const Philox4 x = philox4x32_10(0u, (uint32_t)tile, (uint32_t)k, (uint32_t)b, a.key0, a.key1);
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t sp = spread_bits(x.v[w]);
+            for (int s = 0; s <= a.delay; ++s) {
+                const int p = (npl - s) % npl;
+                a.ring[(((size_t)p * a.n_cb + cb) * kNB + c) * words + tile * 4 + w] = sp;
+            }
+            v4i* dst = reinterpret_cast<v4i*>(is_wg + (size_t)c * np + tile * kTileRows + 32 * w);
+            v4i lo, hi;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t d0 = 0, d1 = 0;
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t v0 = ((x.v[w] >> (4 * q + m)) & 1u) ? 0u : (uint32_t)(-a.alpha) & 0xFFu;
+                    const uint32_t v1 = ((x.v[w] >> (16 + 4 * q + m)) & 1u) ? 0u : (uint32_t)(-a.alpha) & 0xFFu;
+                    d0 |= v0 << (8 * m);
+                    d1 |= v1 << (8 * m);
+                }
+                lo[q] = (int)d0;
+                hi[q] = (int)d1;
+            }
+            dst[0] = lo;
+            dst[1] = hi;
+        }
+    }
+    if (g == 0)
+        for (int lb = threadIdx.x; lb < a.tpw; lb += kThreads) {
+            const int b = b0 + lb;
+            if (b < a.T) {
+                a.best[b] = INT64_MAX;
+                a.first_hit[b] = -1;
+            }
+        }
+}
+
+// Cycle t of column block cb, once every row group has added its energy sums (the previous launch): each
+// replica's H_p (trace), the per-trial minimum and first hit in device memory; the sums are cleared for cycle
+// t + 2.  Wave w takes trials w, w + kWaves, ...; lane k reads replica k (and k + 64, ...).
+template <int kNB>
+__device__ void split_close_cycle(const SweepArgs& a, const int cb, const int t) {
+    const int ln = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int R = a.R, b0 = cb * a.tpw;
+    int32_t* sums = a.e_sum + (size_t)(t & 1) * a.n_cb * kNB + (size_t)cb * kNB;
+    for (int lb = wv; lb < a.tpw; lb += kWaves) {
+        const int b = b0 + lb;
+        int m = INT32_MAX;
+        for (int k = ln; k < R; k += 64) {
+            const int c = lb * R + k;
+            const int e = -sums[c] / 2;
+            if (b < a.T && a.trace) a.trace[(size_t)t * a.T * R + (size_t)b * R + k] = e;
+            m = e < m ? e : m;
+            sums[c] = 0;
+        }
+        int o = __builtin_amdgcn_ds_swizzle(m, (1 << 10) | 0x1F);
+        m = o < m ? o : m;
+        o = __builtin_amdgcn_ds_swizzle(m, (2 << 10) | 0x1F);
+        m = o < m ? o : m;
+        o = __builtin_amdgcn_ds_swizzle(m, (4 << 10) | 0x1F);
+        m = o < m ? o : m;
+        o = __builtin_amdgcn_ds_swizzle(m, (8 << 10) | 0x1F);
+        m = o < m ? o : m;
+        o = __builtin_amdgcn_ds_swizzle(m, (16 << 10) | 0x1F);
+        m = o < m ? o : m;
+        const int lo = __builtin_amdgcn_readlane(m, 0), hi = __builtin_amdgcn_readlane(m, 32);
+        const long long mm = lo < hi ? lo : hi;
+        if (ln == 0 && b < a.T) {
+            if (mm < a.best[b]) a.best[b] = mm;
+            if (a.first_hit[b] < 0 && a.target != INT64_MIN && mm == a.target) a.first_hit[b] = t;
+        }
+    }
+}
+
+// Workgroup state of one split launch at cycle a.t_begin: the column table, cleared energy sums, sigma(t) of
+// every row and sigma(t - d) of the group's rows from the ring in device memory.
+template <int kNB>
+__device__ __forceinline__ void split_block_init(const SweepArgs& a, const int cb, const TileRange tr, const BlockLds& L) {
+    const int np = a.prob.np, words = np / 32;
+    const int npl = L.npl, plane_words = L.plane_words, cstride = L.cstride;
+    const int R = a.R, b0 = cb * a.tpw;
+    const int t = a.t_begin;
+    const int tid = threadIdx.x;
+    for (int c = tid; c < kNB; c += kThreads) {
+        L.e_acc[c] = 0;
+        const int lb = c / R;
+        const int k = c - lb * R;
+        const bool real = c < a.cols_wg;
+        const bool valid = real && (b0 + lb < a.T);
+        const int c_up = real ? lb * R + (k + 1 == R ? 0 : k + 1) : c;
+        const int c_dn = real ? lb * R + (k == 0 ? R - 1 : k - 1) : c;
+        L.colinfo[c] = (uint32_t)c_up | ((uint32_t)c_dn << 8) | ((uint32_t)k << 16) | ((uint32_t)(lb & 0x7F) << 24) |
+                       ((uint32_t)valid << 31);
+    }
+    const int p_cur = t % npl;
+    const uint32_t* src = a.ring + ((size_t)p_cur * a.n_cb + cb) * kNB * words;
+    for (int u = tid; u < kNB * words; u += kThreads) {
+        const int c = u / words;
+        L.planes[p_cur * plane_words + c * cstride + (u - c * words)] = src[u];
+    }
+    if (a.delay > 0) {
+        const int p_del = (t - a.delay + npl) % npl;
+        const uint32_t* dsrc = a.ring + ((size_t)p_del * a.n_cb + cb) * kNB * words;
+        const int gw = 4 * (tr.hi - tr.lo);
+        for (int u = tid; u < kNB * gw; u += kThreads) {
+            const int c = u / gw;
+            const int w = 4 * tr.lo + (u - c * gw);
+            L.planes[p_del * plane_words + c * cstride + w] = dsrc[(size_t)c * words + w];
+        }
+    }
+    __syncthreads();
+}
+
+// End of a split launch: sigma(t + 1) of the group's rows back to the ring, and the group's energy sums added
+// to the column block's totals for cycle t.
+template <int kNB>
+__device__ __forceinline__ void split_block_close(const SweepArgs& a, const int cb, const TileRange tr, const int t,
+                                                  const bool update, const BlockLds& L) {
+    const int np = a.prob.np, words = np / 32;
+    __syncthreads();
+    if (update) {
+        const int p_next = (t + 1) % L.npl;
+        uint32_t* dst = a.ring + ((size_t)p_next * a.n_cb + cb) * kNB * words;
+        const int gw = 4 * (tr.hi - tr.lo);
+        for (int u = threadIdx.x; u < kNB * gw; u += kThreads) {
+            const int c = u / gw;
+            const int w = 4 * tr.lo + (u - c * gw);
+            dst[(size_t)c * words + w] = L.planes[p_next * L.plane_words + c * L.cstride + w];
+        }
+    }
+    if (tr.hi > tr.lo) {
+        int32_t* sums = a.e_sum + (size_t)(t & 1) * a.n_cb * kNB + (size_t)cb * kNB;
+        for (int c = threadIdx.x; c < kNB; c += kThreads)
+            if (L.colinfo[c] >> 31) atomicAdd(&sums[c], L.e_acc[c]);
+    }
+}
+
 // LDS layout of one workgroup (dynamic shared memory, 32-bit words):
 //   planes  [d + 2][kNB][np / 32 + 1]   sigma bit planes (ring), kNB = 16 kNBF columns
 //   noise   [kWaves][kNB][4]            one Philox block per column, exchanged inside the wave
@@ -561,8 +723,9 @@ __device__ __forceinline__ void block_close(const SweepArgs& a, const int wg, co
 //   colinfo [kNB]   u32                 ring neighbours, replica and trial of each column
 //   rows    [kWaves][256] int32         row vectors of each wave's current tile
 // All cycles [a.t_begin, a.t_end] of column block `wg` of one anneal (a persistent workgroup).
-template <bool kFast, int kMode, int kNBF, bool kFp4>
-__device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
+// With kSplit, one cycle (a.t_begin) of row group `group` of column block `wg` (the row-split form).
+template <bool kFast, int kMode, int kNBF, bool kFp4, bool kSplit = false>
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, const int group = 0) {
     constexpr int kNB = 16 * kNBF;
     extern __shared__ uint32_t lds[];
     const int np = a.prob.np;
@@ -586,7 +749,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
     int8_t* is_wg = a.is_state + (size_t)wg * kNB * np;
 
     const BlockLds L{planes, npl, plane_words, cstride, e_acc, hit_l, best_l, colinfo};
-    block_init<kNB>(a, wg, L);
+    // Row tiles of this workgroup: all of them, or the group's range in the row-split form.
+    const TileRange tr = kSplit ? group_tiles(a, group) : TileRange{0, ntiles};
+    if constexpr (kSplit) split_block_init<kNB>(a, wg, tr, L);
+    else block_init<kNB>(a, wg, L);
 
     // 128-column blocks with int8 operands take single-plane problems only (the host checks it): a Horner
     // update of 256 AGPR accumulators would need more VGPRs than are left beside them.
@@ -842,19 +1008,43 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg) {
         } else {
             // A wave without a tile (fewer tiles than waves) fetches the last tile's row vectors instead, so that
             // the load stays inside the row vectors; it never uses them.
-            rowv_next = fetch_rows(a.prob, wave < ntiles ? wave : ntiles - 1);
-            for (int tile = wave; tile < ntiles; tile += kWaves)
-                tile_body(std::integral_constant<int, kNBF>{}, tile, 0, tile + kWaves < ntiles, tile + kWaves);
+            rowv_next = fetch_rows(a.prob, tr.lo + wave < tr.hi ? tr.lo + wave : ntiles - 1);
+            for (int tile = tr.lo + wave; tile < tr.hi; tile += kWaves)
+                tile_body(std::integral_constant<int, kNBF>{}, tile, 0, tile + kWaves < tr.hi, tile + kWaves);
         }
-        cycle_close<kNB>(a, wg, t, L);
+        if constexpr (kSplit) split_block_close<kNB>(a, wg, tr, t, update, L);
+        else cycle_close<kNB>(a, wg, t, L);
     }
 
-    block_close<kNB>(a, wg, L);
+    if constexpr (!kSplit) block_close<kNB>(a, wg, L);
 }
 
 template <bool kFast, int kMode, int kNBF, bool kFp4>
 __global__ __launch_bounds__(kThreads, kNBF == 8 ? 1 : 2) void sweep_kernel(SweepArgs a) {
     sweep_block<kFast, kMode, kNBF, kFp4>(a, blockIdx.x);
+}
+
+// One cycle t of a row-split anneal (flags kSplit*): workgroup blockIdx.x is row group blockIdx.x % n_groups of
+// column block blockIdx.x / n_groups, so that with n_groups a multiple of the XCD count every column block's
+// copy of a row group runs on one XCD and their J rows meet in its L2.
+template <bool kFast, int kMode, int kNBF, bool kFp4>
+__global__ __launch_bounds__(kThreads, 2) void sweep_split_kernel(const SweepArgs* __restrict__ item, int t, int flags) {
+    SweepArgs a = *item;
+    const int cb = blockIdx.x / a.n_groups;
+    const int g = blockIdx.x - cb * a.n_groups;
+    if (flags & kSplitInit) {
+        split_init_state<16 * kNBF>(a, cb, g);
+        return;
+    }
+    if ((flags & kSplitClose) && g == 0) split_close_cycle<16 * kNBF>(a, cb, t - 1);
+    if (flags & kSplitRun) {
+        const bool update = (flags & kSplitUpdate) != 0;
+        a.t_begin = t;
+        a.t_end = update ? t + 1 : t;
+        a.final_pass = update ? 0 : 1;
+        a.save_hist = 0;
+        sweep_block<kFast, kMode, kNBF, kFp4, true>(a, cb, g);
+    }
 }
 
 // Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
@@ -1070,6 +1260,11 @@ hipError_t configure_variant() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_batch_kernel<kFast, kMode, kNBF, kFp4>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if constexpr (kNBF != 8) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_split_kernel<kFast, kMode, kNBF, kFp4>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    }
     return e;
 }
 
@@ -1115,6 +1310,27 @@ hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int 
         break;
         SSQA_FOR_EACH_VARIANT(SSQA_LAUNCH_BATCH)
 #undef SSQA_LAUNCH_BATCH
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int t, int flags, hipStream_t stream) {
+    const hipError_t ce = configure_sweep_kernels();
+    if (ce != hipSuccess) return ce;
+    const size_t lds = (flags & kSplitRun) ? sweep_lds_bytes(host.prob.np, host.delay, host.nb) : 0;
+    const dim3 grid(host.n_cb * host.n_groups), block(kThreads);
+    switch (sweep_variant(host.fast != 0, host.mode, host.nb, host.fp4 != 0)) {
+#define SSQA_LAUNCH_SPLIT(v, al, mo, nbf, f4)                                                                   \
+    case v:                                                                                                   \
+        if constexpr (nbf != 8) {                                                                             \
+            hipLaunchKernelGGL((sweep_split_kernel<al, mo, nbf, f4>), grid, block, lds, stream, item, t, flags); \
+            break;                                                                                            \
+        } else {                                                                                              \
+            return hipErrorInvalidValue;                                                                      \
+        }
+        SSQA_FOR_EACH_VARIANT(SSQA_LAUNCH_SPLIT)
+#undef SSQA_LAUNCH_SPLIT
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
