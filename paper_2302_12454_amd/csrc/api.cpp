@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -448,27 +449,93 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     *out = nullptr;
     if (n < 1 || n > 16384) return fail(SSQA_EINVAL, "n_spins = %d outside [1, 16384]", n);
     if (!h || !J) return fail(SSQA_EINVAL, "h or J is NULL");
-    long long total = 0;
-    int planes = 1;
-    bool fp4_codes = true;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6}
-    long long fp4_bound = 0;      // max_i (|h_i| + 2 sum_j |J_ij|), see fp4_fits
-    for (int i = 0; i < n; ++i) {
-        total += 2LL * std::llabs((long long)h[i]);
-        long long row_abs = 0;
-        if (J[(size_t)i * n + i] != 0) return fail(SSQA_EINVAL, "J[%d][%d] = %d, diagonal must be zero", i, i,
-                                                   J[(size_t)i * n + i]);
-        for (int j = 0; j < n; ++j) {
-            const int32_t v = J[(size_t)i * n + j];
-            if (v != J[(size_t)j * n + i]) return fail(SSQA_EINVAL, "J not symmetric at (%d, %d)", i, j);
-            total += std::llabs((long long)v);
-            row_abs += std::llabs((long long)v);
-            planes = std::max(planes, planes_needed(v));
-            const int m = v < 0 ? -v : v;
-            if (m > 6 || m == 5) fp4_codes = false;
+    // Checks and statistics of J in one pass per row block, over host threads for large N (each pass streams
+    // N^2 int32 values, 400 MB at N = 10^4):
+    //   symmetry, 64 x 64 blocks against their mirrors (a column-order scan would miss the cache on every
+    //   element), and per row the zero diagonal, sum |J_ij|, extremes and whether every entry has an fp4 code.
+    // Failures are reported in a fixed order (first asymmetric pair in row order, then first non-zero diagonal
+    // entry, then the range), whatever the thread count.
+    constexpr int kB = 64;
+    const int nblk = (n + kB - 1) / kB;
+    struct Part {
+        long long first_asym = -1;
+        int first_diag = -1;
+        long long total = 0;       // sum |J_ij| + 2 sum |h_i| over the part's rows
+        int planes = 1;
+        bool codes = true;
+        long long bound = 0;       // max_i (|h_i| + 2 sum_j |J_ij|)
+    };
+    auto scan = [&](int blk_lo, int blk_hi, Part& part) {
+        for (int b = blk_lo; b < blk_hi; ++b) {
+            const int bi = b * kB, ie = std::min(n, bi + kB);
+            for (int bj = bi; bj < n; bj += kB) {
+                const int je = std::min(n, bj + kB);
+                for (int i = bi; i < ie; ++i)
+                    for (int j = std::max(bj, i + 1); j < je; ++j)
+                        if (J[(size_t)i * n + j] != J[(size_t)j * n + i]) {
+                            const long long k = (long long)i * n + j;
+                            if (part.first_asym < 0 || k < part.first_asym) part.first_asym = k;
+                        }
+            }
+            for (int i = bi; i < ie; ++i) {
+                const int32_t* row = J + (size_t)i * n;
+                if (row[i] != 0 && part.first_diag < 0) part.first_diag = i;
+                // The balanced base-256 digits a value needs grow with its distance from zero on either side,
+                // so the row's extremes decide its plane count.
+                long long row_abs = 0;
+                int32_t vmin = 0, vmax = 0;
+                int bad_codes = 0;
+                for (int j = 0; j < n; ++j) {
+                    const int32_t v = row[j];
+                    const long long m = v < 0 ? -(long long)v : (long long)v;
+                    row_abs += m;
+                    vmin = std::min(vmin, v);
+                    vmax = std::max(vmax, v);
+                    bad_codes |= (m > 6) | (m == 5);
+                }
+                const long long ha = std::llabs((long long)h[i]);
+                part.total += row_abs + 2 * ha;
+                part.planes = std::max({part.planes, planes_needed(vmin), planes_needed(vmax)});
+                if (bad_codes) part.codes = false;
+                part.bound = std::max(part.bound, ha + 2 * row_abs);
+            }
         }
-        fp4_bound = std::max(fp4_bound, std::llabs((long long)h[i]) + 2 * row_abs);
-        if (total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
+    };
+    const int threads = (long long)n * n >= (1LL << 22)
+                            ? std::max(1, std::min({8, nblk, (int)std::thread::hardware_concurrency()}))
+                            : 1;
+    std::vector<Part> parts(threads);
+    if (threads == 1) {
+        scan(0, nblk, parts[0]);
+    } else {
+        // Row blocks dealt in an interleaved order, since the symmetry work of block b shrinks with b.
+        std::vector<std::thread> pool;
+        std::vector<std::vector<int>> mine(threads);
+        for (int b = 0; b < nblk; ++b) mine[b % threads].push_back(b);
+        for (int w = 0; w < threads; ++w)
+            pool.emplace_back([&, w] {
+                for (const int b : mine[w]) scan(b, b + 1, parts[w]);
+            });
+        for (std::thread& th : pool) th.join();
     }
+    Part all;
+    for (const Part& q : parts) {
+        if (q.first_asym >= 0 && (all.first_asym < 0 || q.first_asym < all.first_asym)) all.first_asym = q.first_asym;
+        if (q.first_diag >= 0 && (all.first_diag < 0 || q.first_diag < all.first_diag)) all.first_diag = q.first_diag;
+        all.total += q.total;
+        all.planes = std::max(all.planes, q.planes);
+        all.codes = all.codes && q.codes;
+        all.bound = std::max(all.bound, q.bound);
+    }
+    if (all.first_asym >= 0)
+        return fail(SSQA_EINVAL, "J not symmetric at (%d, %d)", (int)(all.first_asym / n), (int)(all.first_asym % n));
+    if (all.first_diag >= 0)
+        return fail(SSQA_EINVAL, "J[%d][%d] = %d, diagonal must be zero", all.first_diag, all.first_diag,
+                    J[(size_t)all.first_diag * n + all.first_diag]);
+    if (all.total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
+    const int planes = all.planes;
+    const bool fp4_codes = all.codes;     // every J_ij in {0, +-1, +-2, +-3, +-4, +-6}
+    const long long fp4_bound = all.bound;   // max_i (|h_i| + 2 sum_j |J_ij|), see fp4_fits
     // The fp4 copy is built when J is representable and at least an anneal without noise and coupling keeps
     // the fp32 accumulation exact; each anneal checks its own bound (fp4_fits).
     const bool fp4_exact = fp4_codes && fp4_bound + 128 < (1LL << 22);

@@ -153,6 +153,25 @@ static void abi_checks() {
     std::vector<int32_t> Jbig((size_t)n * n, 1 << 28);
     for (int i = 0; i < n; ++i) Jbig[(size_t)i * n + i] = 0;
     EXPECT(ssqa_create_problem(n, h.data(), Jbig.data(), 0, &p) == SSQA_ERANGE);
+    {
+        // a size whose checks run over host threads: an asymmetric pair and a diagonal entry are found
+        const int big = 2100;
+        std::vector<int32_t> hb(big, 1), Jb2((size_t)big * big, 0);
+        for (int i = 0; i < big; ++i)
+            for (int j = 0; j < big; ++j)
+                if (i != j) Jb2[(size_t)i * big + j] = -3 * ((i + j) % 3);
+        Jb2[(size_t)1500 * big + 77] = 5;
+        EXPECT(ssqa_create_problem(big, hb.data(), Jb2.data(), 0, &p) == SSQA_EINVAL);
+        EXPECT(std::strstr(ssqa_last_error(), "(77, 1500)") != nullptr);
+        Jb2[(size_t)1500 * big + 77] = Jb2[(size_t)77 * big + 1500];
+        Jb2[(size_t)2000 * big + 2000] = 1;
+        EXPECT(ssqa_create_problem(big, hb.data(), Jb2.data(), 0, &p) == SSQA_EINVAL);
+        EXPECT(std::strstr(ssqa_last_error(), "diagonal") != nullptr);
+        Jb2[(size_t)2000 * big + 2000] = 0;
+        const ssqa_status sb = ssqa_create_problem(big, hb.data(), Jb2.data(), 0, &p);
+        EXPECT(sb == SSQA_OK || sb == SSQA_EDEVICE);
+        if (sb == SSQA_OK) ssqa_destroy_problem(p);
+    }
     const ssqa_status st = ssqa_create_problem(n, h.data(), J.data(), 0, &p);
     EXPECT(st == SSQA_OK || st == SSQA_EDEVICE);   // EDEVICE where no GPU is present
     if (st == SSQA_OK) ssqa_destroy_problem(p);
