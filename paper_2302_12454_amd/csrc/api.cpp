@@ -408,6 +408,153 @@ ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, 
     return SSQA_OK;
 }
 
+// Checks and statistics of J (scan_couplings).
+CouplingScan scan_couplings(int n, const int32_t* h, const int32_t* J, int8_t* J8) {
+    // Checks and statistics of J in one pass per row block, over host threads for large N (each pass streams
+    // N^2 int32 values, 400 MB at N = 10^4):
+    //   symmetry, 64 x 64 blocks against their mirrors (a column-order scan would miss the cache on every
+    //   element), and per row the zero diagonal, sum |J_ij|, extremes and whether every entry has an fp4 code.
+    // Failures are reported in a fixed order (first asymmetric pair in row order, then first non-zero diagonal
+    // entry, then the range), whatever the thread count.
+    constexpr int kB = 64;
+    const int nblk = (n + kB - 1) / kB;
+    auto scan = [&](int blk_lo, int blk_hi, CouplingScan& part) {
+        for (int b = blk_lo; b < blk_hi; ++b) {
+            const int bi = b * kB, ie = std::min(n, bi + kB);
+            for (int bj = bi; bj < n; bj += kB) {
+                const int je = std::min(n, bj + kB);
+                for (int i = bi; i < ie; ++i)
+                    for (int j = std::max(bj, i + 1); j < je; ++j)
+                        if (J[(size_t)i * n + j] != J[(size_t)j * n + i]) {
+                            const long long k = (long long)i * n + j;
+                            if (part.first_asym < 0 || k < part.first_asym) part.first_asym = k;
+                        }
+            }
+            for (int i = bi; i < ie; ++i) {
+                const int32_t* row = J + (size_t)i * n;
+                int8_t* row8 = J8 ? J8 + (size_t)i * n : nullptr;
+                if (row[i] != 0 && part.first_diag < 0) part.first_diag = i;
+                // The balanced base-256 digits a value needs grow with its distance from zero on either side,
+                // so the row's extremes decide its plane count.
+                long long row_abs = 0;
+                int32_t vmin = 0, vmax = 0;
+                int bad_codes = 0;
+                for (int j = 0; j < n; ++j) {
+                    const int32_t v = row[j];
+                    const long long m = v < 0 ? -(long long)v : (long long)v;
+                    row_abs += m;
+                    vmin = std::min(vmin, v);
+                    vmax = std::max(vmax, v);
+                    bad_codes |= (m > 6) | (m == 5);
+                }
+                if (row8)
+                    for (int j = 0; j < n; ++j) row8[j] = (int8_t)row[j];
+                const long long ha = std::llabs((long long)h[i]);
+                part.total += row_abs + 2 * ha;
+                part.planes = std::max({part.planes, planes_needed(vmin), planes_needed(vmax)});
+                if (bad_codes) part.codes = false;
+                part.bound = std::max(part.bound, ha + 2 * row_abs);
+            }
+        }
+    };
+    const int threads = (long long)n * n >= (1LL << 22)
+                            ? std::max(1, std::min({8, nblk, (int)std::thread::hardware_concurrency()}))
+                            : 1;
+    std::vector<CouplingScan> parts(threads);
+    if (threads == 1) {
+        scan(0, nblk, parts[0]);
+    } else {
+        // Row blocks dealt in an interleaved order, since the symmetry work of block b shrinks with b.
+        std::vector<std::thread> pool;
+        std::vector<std::vector<int>> mine(threads);
+        for (int b = 0; b < nblk; ++b) mine[b % threads].push_back(b);
+        for (int w = 0; w < threads; ++w)
+            pool.emplace_back([&, w] {
+                for (const int b : mine[w]) scan(b, b + 1, parts[w]);
+            });
+        for (std::thread& th : pool) th.join();
+    }
+    CouplingScan all;
+    for (const CouplingScan& q : parts) {
+        if (q.first_asym >= 0 && (all.first_asym < 0 || q.first_asym < all.first_asym)) all.first_asym = q.first_asym;
+        if (q.first_diag >= 0 && (all.first_diag < 0 || q.first_diag < all.first_diag)) all.first_diag = q.first_diag;
+        all.total += q.total;
+        all.planes = std::max(all.planes, q.planes);
+        all.codes = all.codes && q.codes;
+        all.bound = std::max(all.bound, q.bound);
+    }
+    return all;
+}
+
+// The failure a scan found, in a fixed order: first asymmetric pair in row order, first non-zero diagonal
+// entry, then the int32 range.
+ssqa_status check_couplings(const CouplingScan& all, int n, const int32_t* J) {
+    if (all.first_asym >= 0)
+        return fail(SSQA_EINVAL, "J not symmetric at (%d, %d)", (int)(all.first_asym / n), (int)(all.first_asym % n));
+    if (all.first_diag >= 0)
+        return fail(SSQA_EINVAL, "J[%d][%d] = %d, diagonal must be zero", all.first_diag, all.first_diag,
+                    J[(size_t)all.first_diag * n + all.first_diag]);
+    if (all.total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
+    return SSQA_OK;
+}
+
+ssqa_status create_problem_impl(int32_t n, const int32_t* h, const int32_t* J, const int8_t* J8,
+                                const CouplingScan& sc, int32_t device, ssqa_problem_t* out) {
+    const int planes = sc.planes;
+    const bool fp4_codes = sc.codes;        // every J_ij in {0, +-1, +-2, +-3, +-4, +-6}
+    const long long fp4_bound = sc.bound;   // max_i (|h_i| + 2 sum_j |J_ij|), see fp4_fits
+    // The fp4 copy is built when J is representable and at least an anneal without noise and coupling keeps
+    // the fp32 accumulation exact; each anneal checks its own bound (fp4_fits).
+    const bool fp4_exact = fp4_codes && fp4_bound + 128 < (1LL << 22);
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
+        return fail(SSQA_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= dev_count) return fail(SSQA_EINVAL, "device %d outside [0, %d)", device, dev_count);
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice(%d) failed", device);
+
+    const int np = (n + kTileRows - 1) / kTileRows * kTileRows;
+    ssqa_problem* p = new (std::nothrow) ssqa_problem();
+    if (!p) return fail(SSQA_ENOMEM, "host allocation failed");
+    p->device = device;
+    p->fp4_bound = fp4_bound;
+    void* Jdev = nullptr;   // J on the device as given: int8 (one plane) or int32
+    int32_t* h32 = nullptr;
+    const size_t plane_bytes = (size_t)planes * np * np;
+    const int kp4 = fp4_k_extent(np);
+    hipError_t e = hipMalloc(&p->J_planes, plane_bytes);
+    if (e == hipSuccess && fp4_exact) e = hipMalloc(&p->J_fp4, (size_t)np * kp4 / 2);
+    if (e == hipSuccess) e = hipMalloc(&p->rowvec, (size_t)np * 4 * 3);
+    const int elem = J8 ? 1 : 4;
+    if (e == hipSuccess) e = hipMalloc(&Jdev, (size_t)n * n * elem);
+    if (e == hipSuccess) e = hipMalloc(&h32, (size_t)n * 4);
+    if (e == hipSuccess)
+        e = hipMemcpy(Jdev, J8 ? static_cast<const void*>(J8) : static_cast<const void*>(J), (size_t)n * n * elem,
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h32, h, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_prepare_planes(Jdev, elem, h32, n, np, planes, p->J_planes, p->rowvec, nullptr);
+    if (e == hipSuccess && fp4_exact) e = launch_prepare_fp4(Jdev, elem, n, np, kp4, p->J_fp4, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (Jdev) (void)hipFree(Jdev);
+    if (h32) (void)hipFree(h32);
+    if (e != hipSuccess) {
+        ssqa_destroy_problem(p);
+        return e == hipErrorOutOfMemory ? fail(SSQA_ENOMEM, "device allocation failed")
+                                        : hip_fail(e, "create_problem");
+    }
+    p->dev.n = n;
+    p->dev.np = np;
+    p->dev.planes = planes;
+    p->dev.J = p->J_planes;
+    p->dev.J4 = p->J_fp4;
+    p->dev.kp4 = kp4;
+    p->dev.h = p->rowvec;
+    p->dev.hr = p->rowvec + np;
+    p->dev.er = p->rowvec + 2 * np;
+    *out = p;
+    return SSQA_OK;
+}
+
 }  // namespace detail
 }  // namespace ssqa
 
@@ -449,140 +596,10 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     *out = nullptr;
     if (n < 1 || n > 16384) return fail(SSQA_EINVAL, "n_spins = %d outside [1, 16384]", n);
     if (!h || !J) return fail(SSQA_EINVAL, "h or J is NULL");
-    // Checks and statistics of J in one pass per row block, over host threads for large N (each pass streams
-    // N^2 int32 values, 400 MB at N = 10^4):
-    //   symmetry, 64 x 64 blocks against their mirrors (a column-order scan would miss the cache on every
-    //   element), and per row the zero diagonal, sum |J_ij|, extremes and whether every entry has an fp4 code.
-    // Failures are reported in a fixed order (first asymmetric pair in row order, then first non-zero diagonal
-    // entry, then the range), whatever the thread count.
-    constexpr int kB = 64;
-    const int nblk = (n + kB - 1) / kB;
-    struct Part {
-        long long first_asym = -1;
-        int first_diag = -1;
-        long long total = 0;       // sum |J_ij| + 2 sum |h_i| over the part's rows
-        int planes = 1;
-        bool codes = true;
-        long long bound = 0;       // max_i (|h_i| + 2 sum_j |J_ij|)
-    };
-    auto scan = [&](int blk_lo, int blk_hi, Part& part) {
-        for (int b = blk_lo; b < blk_hi; ++b) {
-            const int bi = b * kB, ie = std::min(n, bi + kB);
-            for (int bj = bi; bj < n; bj += kB) {
-                const int je = std::min(n, bj + kB);
-                for (int i = bi; i < ie; ++i)
-                    for (int j = std::max(bj, i + 1); j < je; ++j)
-                        if (J[(size_t)i * n + j] != J[(size_t)j * n + i]) {
-                            const long long k = (long long)i * n + j;
-                            if (part.first_asym < 0 || k < part.first_asym) part.first_asym = k;
-                        }
-            }
-            for (int i = bi; i < ie; ++i) {
-                const int32_t* row = J + (size_t)i * n;
-                if (row[i] != 0 && part.first_diag < 0) part.first_diag = i;
-                // The balanced base-256 digits a value needs grow with its distance from zero on either side,
-                // so the row's extremes decide its plane count.
-                long long row_abs = 0;
-                int32_t vmin = 0, vmax = 0;
-                int bad_codes = 0;
-                for (int j = 0; j < n; ++j) {
-                    const int32_t v = row[j];
-                    const long long m = v < 0 ? -(long long)v : (long long)v;
-                    row_abs += m;
-                    vmin = std::min(vmin, v);
-                    vmax = std::max(vmax, v);
-                    bad_codes |= (m > 6) | (m == 5);
-                }
-                const long long ha = std::llabs((long long)h[i]);
-                part.total += row_abs + 2 * ha;
-                part.planes = std::max({part.planes, planes_needed(vmin), planes_needed(vmax)});
-                if (bad_codes) part.codes = false;
-                part.bound = std::max(part.bound, ha + 2 * row_abs);
-            }
-        }
-    };
-    const int threads = (long long)n * n >= (1LL << 22)
-                            ? std::max(1, std::min({8, nblk, (int)std::thread::hardware_concurrency()}))
-                            : 1;
-    std::vector<Part> parts(threads);
-    if (threads == 1) {
-        scan(0, nblk, parts[0]);
-    } else {
-        // Row blocks dealt in an interleaved order, since the symmetry work of block b shrinks with b.
-        std::vector<std::thread> pool;
-        std::vector<std::vector<int>> mine(threads);
-        for (int b = 0; b < nblk; ++b) mine[b % threads].push_back(b);
-        for (int w = 0; w < threads; ++w)
-            pool.emplace_back([&, w] {
-                for (const int b : mine[w]) scan(b, b + 1, parts[w]);
-            });
-        for (std::thread& th : pool) th.join();
-    }
-    Part all;
-    for (const Part& q : parts) {
-        if (q.first_asym >= 0 && (all.first_asym < 0 || q.first_asym < all.first_asym)) all.first_asym = q.first_asym;
-        if (q.first_diag >= 0 && (all.first_diag < 0 || q.first_diag < all.first_diag)) all.first_diag = q.first_diag;
-        all.total += q.total;
-        all.planes = std::max(all.planes, q.planes);
-        all.codes = all.codes && q.codes;
-        all.bound = std::max(all.bound, q.bound);
-    }
-    if (all.first_asym >= 0)
-        return fail(SSQA_EINVAL, "J not symmetric at (%d, %d)", (int)(all.first_asym / n), (int)(all.first_asym % n));
-    if (all.first_diag >= 0)
-        return fail(SSQA_EINVAL, "J[%d][%d] = %d, diagonal must be zero", all.first_diag, all.first_diag,
-                    J[(size_t)all.first_diag * n + all.first_diag]);
-    if (all.total >= (1LL << 30)) return fail(SSQA_ERANGE, "2 sum|h| + sum|J| >= 2^30: int32 fields could overflow");
-    const int planes = all.planes;
-    const bool fp4_codes = all.codes;     // every J_ij in {0, +-1, +-2, +-3, +-4, +-6}
-    const long long fp4_bound = all.bound;   // max_i (|h_i| + 2 sum_j |J_ij|), see fp4_fits
-    // The fp4 copy is built when J is representable and at least an anneal without noise and coupling keeps
-    // the fp32 accumulation exact; each anneal checks its own bound (fp4_fits).
-    const bool fp4_exact = fp4_codes && fp4_bound + 128 < (1LL << 22);
-    int dev_count = 0;
-    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
-        return fail(SSQA_EDEVICE, "no HIP device available");
-    if (device < 0 || device >= dev_count) return fail(SSQA_EINVAL, "device %d outside [0, %d)", device, dev_count);
-    DeviceGuard guard(device);
-    if (!guard.ok) return fail(SSQA_EDEVICE, "hipSetDevice(%d) failed", device);
-
-    const int np = (n + kTileRows - 1) / kTileRows * kTileRows;
-    ssqa_problem* p = new (std::nothrow) ssqa_problem();
-    if (!p) return fail(SSQA_ENOMEM, "host allocation failed");
-    p->device = device;
-    p->fp4_bound = fp4_bound;
-    int32_t* J32 = nullptr;
-    int32_t* h32 = nullptr;
-    const size_t plane_bytes = (size_t)planes * np * np;
-    const int kp4 = fp4_k_extent(np);
-    hipError_t e = hipMalloc(&p->J_planes, plane_bytes);
-    if (e == hipSuccess && fp4_exact) e = hipMalloc(&p->J_fp4, (size_t)np * kp4 / 2);
-    if (e == hipSuccess) e = hipMalloc(&p->rowvec, (size_t)np * 4 * 3);
-    if (e == hipSuccess) e = hipMalloc(&J32, (size_t)n * n * 4);
-    if (e == hipSuccess) e = hipMalloc(&h32, (size_t)n * 4);
-    if (e == hipSuccess) e = hipMemcpy(J32, J, (size_t)n * n * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h32, h, (size_t)n * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_prepare_planes(J32, h32, n, np, planes, p->J_planes, p->rowvec, nullptr);
-    if (e == hipSuccess && fp4_exact) e = launch_prepare_fp4(J32, n, np, kp4, p->J_fp4, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (J32) (void)hipFree(J32);
-    if (h32) (void)hipFree(h32);
-    if (e != hipSuccess) {
-        ssqa_destroy_problem(p);
-        return e == hipErrorOutOfMemory ? fail(SSQA_ENOMEM, "device allocation failed")
-                                        : hip_fail(e, "create_problem");
-    }
-    p->dev.n = n;
-    p->dev.np = np;
-    p->dev.planes = planes;
-    p->dev.J = p->J_planes;
-    p->dev.J4 = p->J_fp4;
-    p->dev.kp4 = kp4;
-    p->dev.h = p->rowvec;
-    p->dev.hr = p->rowvec + np;
-    p->dev.er = p->rowvec + 2 * np;
-    *out = p;
-    return SSQA_OK;
+    const CouplingScan sc = scan_couplings(n, h, J, nullptr);
+    const ssqa_status st = check_couplings(sc, n, J);
+    if (st != SSQA_OK) return st;
+    return create_problem_impl(n, h, J, nullptr, sc, device, out);
 }
 
 void ssqa_destroy_problem(ssqa_problem_t p) {

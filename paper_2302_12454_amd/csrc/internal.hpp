@@ -109,10 +109,12 @@ constexpr int kSplitUpdate = 8;
 
 // Launchers (sweep.hip).  Return hipSuccess or the launch error.
 // rowvec receives [h | hr | er], three int32 vectors of np entries.
-hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
+// J is device int32 [n * n] (elem = 4) or, for a single-plane problem, int8 (elem = 1).
+hipError_t launch_prepare_planes(const void* J, int elem, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
                                  int8_t* Jp, int32_t* rowvec, hipStream_t stream);
 // fp4 copy of J (every entry must be one of 0, +-1, +-2, +-3, +-4, +-6): np rows by kp4 columns.
-hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4, hipStream_t stream);
+hipError_t launch_prepare_fp4(const void* J, int elem, int32_t n, int32_t np, int32_t kp4, uint8_t* J4,
+                              hipStream_t stream);
 // Sets the LDS limits of every sweep kernel variant once (before any launch or graph capture).
 hipError_t configure_sweep_kernels();
 // Dynamic LDS of one sweep workgroup for padded size np, delay d and nb columns.
@@ -208,6 +210,23 @@ struct DeviceGuard {
     ~DeviceGuard();
 };
 
+// Checks and statistics of a host coupling matrix J (int32 [n * n]) with biases h.
+struct CouplingScan {
+    long long first_asym = -1;   // first asymmetric pair in row order (i * n + j), or -1
+    int first_diag = -1;         // first row with a non-zero diagonal entry, or -1
+    long long total = 0;         // 2 sum_i |h_i| + sum_ij |J_ij|
+    int planes = 1;              // balanced int8 planes J needs
+    bool codes = true;           // every J_ij is one of 0, +-1, +-2, +-3, +-4, +-6 (fp4 codes)
+    long long bound = 0;         // max_i (|h_i| + 2 sum_j |J_ij|)
+};
+// One pass over J, in 64 x 64 blocks and over host threads for large n; with J8 non-null it also writes J
+// narrowed to int8 there (exact when planes == 1).
+CouplingScan scan_couplings(int n, const int32_t* h, const int32_t* J, int8_t* J8);
+// The failure a scan found (first asymmetric pair, first non-zero diagonal entry, then the int32 range).
+ssqa_status check_couplings(const CouplingScan& scan, int n, const int32_t* J);
+// ssqa_create_problem after a passed check: J on the host as int32, or (J8 non-null, planes == 1) as int8.
+ssqa_status create_problem_impl(int32_t n, const int32_t* h, const int32_t* J, const int8_t* J8,
+                                const CouplingScan& scan, int32_t device, ssqa_problem_t* out);
 // Whether the fp4 field product of an anneal of `prob` with `pa` is exact (schedules already checked).
 bool fp4_fits(const ssqa_problem* prob, const ssqa_anneal_params* pa);
 // Whether the byte-parallel epilogue applies to `pa` over its whole schedule (alpha = 1 and small increments).

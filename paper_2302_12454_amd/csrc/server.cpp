@@ -43,7 +43,9 @@ struct Request {
     int32_t early_exit = 0;
     int n = 0;
     int planes = 1;
-    std::vector<int32_t> h, J;           // host copies until admission
+    std::vector<int32_t> h, J;           // host copies until admission (J as int32 only when it needs planes > 1)
+    std::unique_ptr<int8_t[]> J8;        // J narrowed to int8 (one plane), until admission
+    CouplingScan scan;                   // checks and statistics of J, from submit
     ssqa_anneal_params params{};
     std::vector<int32_t> jperp, i0;
     // device side, from admission to retirement
@@ -117,10 +119,13 @@ struct ssqa_server {
     std::vector<uint32_t> work;
     int64_t cycles_run = 0;
     double spin_updates = 0;
-    // second stream of the row-split requests' launches, and the events that fork it from and join it to the
-    // caller's stream (created at the first split request)
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    // streams of the row-split requests' launches (request k of a step on stream k mod kSideStreams, so that
+    // several large requests advance together), the event that forks them from the caller's stream and one
+    // per stream that joins it back (created at the first split request)
+    static constexpr int kSideStreams = 4;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
 };
 
 namespace {
@@ -134,7 +139,9 @@ void release_device(Request* r) {
 
 // Upload the problem and allocate the request's state; returns SSQA_OK or the failure.
 ssqa_status admit(ssqa_server* s, Request* r) {
-    ssqa_status st = ssqa_create_problem(r->n, r->h.data(), r->J.data(), s->cfg.device, &r->prob);
+    // J was checked at submit; its int8 copy (or int32 one when it needs several planes) goes to the device
+    ssqa_status st = create_problem_impl(r->n, r->h.data(), r->J8 ? nullptr : r->J.data(), r->J8.get(), r->scan,
+                                         s->cfg.device, &r->prob);
     if (st != SSQA_OK) return st;
     ssqa_anneal_params& pa = r->params;
     pa.jperp = r->jperp.data();
@@ -201,6 +208,7 @@ ssqa_status admit(ssqa_server* s, Request* r) {
     // host copies of the problem are no longer needed
     std::vector<int32_t>().swap(r->h);
     std::vector<int32_t>().swap(r->J);
+    r->J8.reset();
     return SSQA_OK;
 }
 
@@ -245,27 +253,25 @@ ssqa_status ssqa_server_submit(ssqa_server_t s, const ssqa_request* req, int64_t
     if (blocks > 65535)
         return fail(SSQA_EINVAL, "request needs %lld workgroups of whole trials (> 65535): fewer trials per request",
                     (long long)blocks);
+    // J is checked here, once (a J the problem upload would refuse is refused at submit), and kept as int8 when
+    // it fits one plane: a quarter of the host memory to copy and of the bytes to upload at admission.
+    const int n = req->n_spins;
+    std::unique_ptr<int8_t[]> j8(new (std::nothrow) int8_t[(size_t)n * n]);
+    const CouplingScan sc = scan_couplings(n, req->h, req->J, j8.get());
+    const ssqa_status st = check_couplings(sc, n, req->J);
+    if (st != SSQA_OK) return st;
     auto r = std::make_unique<Request>();
     r->id = s->next_id++;
-    r->n = req->n_spins;
+    r->n = n;
     r->early_exit = req->early_exit;
-    r->h.assign(req->h, req->h + req->n_spins);
-    r->J.assign(req->J, req->J + (size_t)req->n_spins * req->n_spins);
+    r->h.assign(req->h, req->h + n);
+    if (sc.planes == 1 && j8) r->J8 = std::move(j8);
+    else r->J.assign(req->J, req->J + (size_t)n * n);
+    r->scan = sc;
     r->params = pa;
     r->jperp.assign(pa.jperp, pa.jperp + pa.cycles);
     r->i0.assign(pa.i0, pa.i0 + pa.cycles);
-    // int8 planes needed by J (balanced base-256 digits), for the memory charge before admission
-    int planes = 1;
-    for (int32_t v : r->J) {
-        int p = 0;
-        do {
-            const int8_t d = (int8_t)(v & 0xFF);
-            v = (v - d) >> 8;
-            ++p;
-        } while (v != 0);
-        planes = std::max(planes, p);
-    }
-    r->planes = planes;
+    r->planes = sc.planes;
     r->submit_s = now_s(s->t0);
     s->queue.push_back(r.get());
     *id = r->id;
@@ -387,38 +393,47 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
     // Row-split requests: their K cycles as one launch per cycle on the second stream, beside the persistent
     // launches below.  Launch t closes cycle t - 1 (except the step's first) and runs cycle t; a last launch
     // closes the step's last cycle, so that best energies and first hits are current at the readback.
+    int used = 0;   // side streams this step
     if (any_split) {
-        if (!s->side) {
-            SSQA_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking), "side stream");
+        if (!s->fork) {
             SSQA_HIP(hipEventCreateWithFlags(&s->fork, hipEventDisableTiming), "event");
-            SSQA_HIP(hipEventCreateWithFlags(&s->join, hipEventDisableTiming), "event");
+            for (int k = 0; k < ssqa_server::kSideStreams; ++k) {
+                SSQA_HIP(hipStreamCreateWithFlags(&s->side[k], hipStreamNonBlocking), "side stream");
+                SSQA_HIP(hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming), "event");
+            }
         }
         SSQA_HIP(hipEventRecord(s->fork, stream), "fork");
-        SSQA_HIP(hipStreamWaitEvent(s->side, s->fork, 0), "fork");
+        int next = 0;
         for (int i = 0; i < n; ++i) {
             Request* r = s->active[i];
             if (!r->split) continue;
+            const int k = next++ % ssqa_server::kSideStreams;
+            hipStream_t side = s->side[k];
+            if (k >= used) {
+                SSQA_HIP(hipStreamWaitEvent(side, s->fork, 0), "fork");
+                used = k + 1;
+            }
             const SweepArgs& a = s->items[i];
             const int c0 = a.t_begin, c1 = a.t_end;
-            if (c0 == 0) SSQA_HIP(launch_sweep_split(r->d_args, a, 0, kSplitInit, s->side), "split init");
+            if (c0 == 0) SSQA_HIP(launch_sweep_split(r->d_args, a, 0, kSplitInit, side), "split init");
             for (int t = c0; t < c1; ++t)
                 SSQA_HIP(launch_sweep_split(r->d_args, a, t, kSplitRun | kSplitUpdate | (t > c0 ? kSplitClose : 0),
-                                            s->side), "split cycle");
+                                            side), "split cycle");
             int last = c1 - 1;
             if (a.final_pass) {   // the energy of sigma(SC)
-                SSQA_HIP(launch_sweep_split(r->d_args, a, c1, kSplitRun | (c1 > c0 ? kSplitClose : 0), s->side),
+                SSQA_HIP(launch_sweep_split(r->d_args, a, c1, kSplitRun | (c1 > c0 ? kSplitClose : 0), side),
                          "split final");
                 last = c1;
             }
-            if (last >= c0) SSQA_HIP(launch_sweep_split(r->d_args, a, last + 1, kSplitClose, s->side), "split close");
+            if (last >= c0) SSQA_HIP(launch_sweep_split(r->d_args, a, last + 1, kSplitClose, side), "split close");
         }
-        SSQA_HIP(hipEventRecord(s->join, s->side), "join");
+        for (int k = 0; k < used; ++k) SSQA_HIP(hipEventRecord(s->join[k], s->side[k]), "join");
     }
     for (int v = 0; v < kVariants; ++v) {
         if (!len[v]) continue;
         SSQA_HIP(launch_sweep_batch(d_items, d_work + off[v], (int)len[v], max_np[v], max_delay[v], v, stream), "step");
     }
-    if (any_split) SSQA_HIP(hipStreamWaitEvent(stream, s->join, 0), "join");
+    for (int k = 0; k < used; ++k) SSQA_HIP(hipStreamWaitEvent(stream, s->join[k], 0), "join");
     // 3. read back and retire at the requests' own cycle boundaries
     for (int i = 0; i < n; ++i) {
         Request* r = s->active[i];
@@ -501,12 +516,15 @@ ssqa_status ssqa_server_stats(ssqa_server_t s, ssqa_server_stats_t* out) {
 void ssqa_server_destroy(ssqa_server_t s) {
     if (!s) return;
     DeviceGuard guard(s->cfg.device);
-    if (s->side) (void)hipStreamSynchronize(s->side);
+    for (hipStream_t side : s->side)
+        if (side) (void)hipStreamSynchronize(side);
     for (auto& kv : s->all) release_device(kv.second.get());
     if (s->table) (void)hipFree(s->table);
     if (s->fork) (void)hipEventDestroy(s->fork);
-    if (s->join) (void)hipEventDestroy(s->join);
-    if (s->side) (void)hipStreamDestroy(s->side);
+    for (int k = 0; k < ssqa_server::kSideStreams; ++k) {
+        if (s->join[k]) (void)hipEventDestroy(s->join[k]);
+        if (s->side[k]) (void)hipStreamDestroy(s->side[k]);
+    }
     delete s;
 }
 

@@ -1057,15 +1057,16 @@ __global__ __launch_bounds__(kThreads, kNBF == 8 ? 1 : 2) void sweep_batch_kerne
     sweep_block<kFast, kMode, kNBF, kFp4>(a, (int)(w & 0xFFFFu));
 }
 
-// int32 J [n][n] -> P balanced int8 planes [P][np][np] (J = sum_p 256^p J_p), zero padded;
-// also the padded h and the row sums of J.
-__global__ void prepare_planes_kernel(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np,
+// J [n][n] (int32, or int8 for a single-plane problem) -> P balanced int8 planes [P][np][np]
+// (J = sum_p 256^p J_p), zero padded; also the padded h and the row sums of J.
+template <typename TJ>
+__global__ void prepare_planes_kernel(const TJ* J32, const int32_t* h32, int32_t n, int32_t np,
                                       int32_t P, int8_t* Jp, int32_t* rowvec) {
     const int i = blockIdx.x;
     if (i >= np) return;
     long long rs = 0;
     for (int j = threadIdx.x; j < np; j += blockDim.x) {
-        int v = (i < n && j < n) ? J32[(size_t)i * n + j] : 0;
+        int v = (i < n && j < n) ? (int)J32[(size_t)i * n + j] : 0;
         rs += v;
         const size_t off = tiled_offset(i, j, np);
         for (int p = 0; p < P; ++p) {
@@ -1098,14 +1099,15 @@ __device__ inline uint32_t fp4_code(int v) {
     return (v < 0 && m != 0) ? (c | 8u) : c;
 }
 
-__global__ void prepare_fp4_kernel(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4) {
+template <typename TJ>
+__global__ void prepare_fp4_kernel(const TJ* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4) {
     const int i = blockIdx.x;
     if (i >= np) return;
     for (int q = threadIdx.x; q < kp4 / 2; q += blockDim.x) {
         const int j0 = (q >> 4) * 32 + (q & 15);      // K offset with bit 4 clear; its partner is j0 + 16
         const int j1 = j0 + 16;
-        const int v0 = (i < n && j0 < n) ? J32[(size_t)i * n + j0] : 0;
-        const int v1 = (i < n && j1 < n) ? J32[(size_t)i * n + j1] : 0;
+        const int v0 = (i < n && j0 < n) ? (int)J32[(size_t)i * n + j0] : 0;
+        const int v1 = (i < n && j1 < n) ? (int)J32[(size_t)i * n + j1] : 0;
         int nib;
         const size_t off = tiled_offset_fp4(i, j0, kp4, &nib);
         J4[off] = (uint8_t)(fp4_code(v0) | (fp4_code(v1) << 4));
@@ -1242,14 +1244,25 @@ size_t sweep_lds_bytes(int np, int delay, int nb) {
            (size_t)nb * 4 + (size_t)kWaves * 256 * 4;
 }
 
-hipError_t launch_prepare_fp4(const int32_t* J32, int32_t n, int32_t np, int32_t kp4, uint8_t* J4, hipStream_t stream) {
-    hipLaunchKernelGGL(prepare_fp4_kernel, dim3(np), dim3(256), 0, stream, J32, n, np, kp4, J4);
+hipError_t launch_prepare_fp4(const void* J, int elem, int32_t n, int32_t np, int32_t kp4, uint8_t* J4,
+                              hipStream_t stream) {
+    if (elem == 1)
+        hipLaunchKernelGGL(prepare_fp4_kernel<int8_t>, dim3(np), dim3(256), 0, stream, static_cast<const int8_t*>(J), n,
+                           np, kp4, J4);
+    else
+        hipLaunchKernelGGL(prepare_fp4_kernel<int32_t>, dim3(np), dim3(256), 0, stream, static_cast<const int32_t*>(J),
+                           n, np, kp4, J4);
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_planes(const int32_t* J32, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
+hipError_t launch_prepare_planes(const void* J, int elem, const int32_t* h32, int32_t n, int32_t np, int32_t planes,
                                  int8_t* Jp, int32_t* rowvec, hipStream_t stream) {
-    hipLaunchKernelGGL(prepare_planes_kernel, dim3(np), dim3(256), 0, stream, J32, h32, n, np, planes, Jp, rowvec);
+    if (elem == 1)
+        hipLaunchKernelGGL(prepare_planes_kernel<int8_t>, dim3(np), dim3(256), 0, stream, static_cast<const int8_t*>(J),
+                           h32, n, np, planes, Jp, rowvec);
+    else
+        hipLaunchKernelGGL(prepare_planes_kernel<int32_t>, dim3(np), dim3(256), 0, stream,
+                           static_cast<const int32_t*>(J), h32, n, np, planes, Jp, rowvec);
     return hipGetLastError();
 }
 

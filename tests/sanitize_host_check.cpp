@@ -204,6 +204,12 @@ static void abi_checks() {
     EXPECT(ssqa_server_submit(s, &r, &id2) == SSQA_EINVAL);
     r = request(n, h, J, q, i0, 1, 65535 * 64 + 1);
     EXPECT(ssqa_server_submit(s, &r, &id2) == SSQA_EINVAL);
+    r = request(n, h, Jb, q, i0, 8, 4);   // the diagonal entry: J is checked at submit
+    EXPECT(ssqa_server_submit(s, &r, &id2) == SSQA_EINVAL);
+    std::vector<int32_t> Jw = J;             // entries beyond int8: kept as int32 until admission
+    Jw[1] = Jw[n] = 1000;
+    r = request(n, h, Jw, q, i0, 8, 4);
+    EXPECT(ssqa_server_submit(s, &r, &id2) == SSQA_OK);
     r = request(n, h, J, q, i0, 33, 3);
     EXPECT(ssqa_server_submit(s, &r, &id2) == SSQA_OK);
     ssqa_request_info info;

@@ -117,3 +117,26 @@ def test_split_beside_persistent_requests_with_early_exit(lib):
     expect = orc.first_hit[0] if 0 <= orc.first_hit[0] < limit else -1
     assert x["first_hit"][3] == expect
     s.close()
+
+
+def test_several_split_requests_at_once(lib):
+    """Five forced-split requests of different sizes in flight together (spread over the server's side streams,
+    two sharing one) beside a persistent one: each equals ssqa_anneal trial for trial."""
+    _note("case several split requests at once")
+    s = lib.Server(cycles_per_step=9, split_rows=512)
+    jobs = []
+    for k, (n, R, T, SC) in enumerate(((700, 8, 10, 30), (520, 16, 6, 25), (1000, 4, 9, 40), (650, 32, 3, 33),
+                                       (800, 8, 8, 20), (90, 8, 5, 30))):
+        h, J = random_ising(n, 300 + k, h_max=60, j_max=4 if k % 2 else 30)
+        rng = np.random.default_rng(300 + k)
+        q = rng.integers(-5, 6, size=SC)
+        i0 = rng.integers(6, 60, size=SC)
+        kw = dict(replicas=R, trials=T, cycles=SC, jperp=q, i0=i0, alpha=1, noise_amp=6, delay=1 + k % 2, seed=k,
+                  coupling_mode=k % 2, target=-10 ** 9)
+        jobs.append((h, J, kw, s.submit(h, J, **kw)))
+    _drain(s, [rid for *_, rid in jobs])
+    for h, J, kw, rid in jobs:
+        x = s.poll(rid)
+        assert x["state"] == "done" and x["cycles_done"] == kw["cycles"]
+        _compare(lib, h, J, kw, x)
+    s.close()

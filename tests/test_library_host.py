@@ -230,6 +230,34 @@ def _submit(lib, n, R, T, SC=10):
     return st, msg
 
 
+def test_server_submit_checks_j(lib):
+    """Submit checks J once, before queueing: a non-symmetric J or a non-zero diagonal is refused with
+    SSQA_EINVAL and a message naming the entry (no device work)."""
+    n, SC = 6, 4
+    h = (ctypes.c_int32 * n)(*([1] * n))
+    q = (ctypes.c_int32 * SC)(*([0] * SC))
+    i0 = (ctypes.c_int32 * SC)(*([24] * SC))
+    cfg = lib_mod.ServerConfig(0, 10, 16, 1 << 30)
+    server = ctypes.c_void_p()
+    assert lib.ssqa_server_create(ctypes.byref(cfg), ctypes.byref(server)) == 0
+    for (i, j, text) in ((1, 4, b"(1, 4)"), (3, 3, b"diagonal")):
+        Jv = [0] * (n * n)
+        Jv[i * n + j] = 2
+        J = (ctypes.c_int32 * (n * n))(*Jv)
+        req = lib_mod.Request()
+        req.n_spins = n
+        req.h = ctypes.cast(h, lib_mod.c_int32_p)
+        req.J = ctypes.cast(J, lib_mod.c_int32_p)
+        p = req.params
+        p.replicas, p.trials, p.cycles, p.delay, p.alpha, p.noise_amp = 4, 2, SC, 1, 1, 12
+        p.jperp = ctypes.cast(q, lib_mod.c_int32_p)
+        p.i0 = ctypes.cast(i0, lib_mod.c_int32_p)
+        rid = ctypes.c_int64()
+        assert lib.ssqa_server_submit(server, ctypes.byref(req), ctypes.byref(rid)) == -1
+        assert text in lib.ssqa_last_error(), lib.ssqa_last_error()
+    lib.ssqa_server_destroy(server)
+
+
 def test_server_submit_bounds_requests(lib):
     """Submit refuses, before any device work, a request whose blocks of whole trials would not fit the 16-bit
     block index of a launch's work code (R = 64: one trial per block, T = 70,000 -> SSQA_EINVAL) and one with
