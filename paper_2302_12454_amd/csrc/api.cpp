@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -596,10 +597,14 @@ ssqa_status ssqa_create_problem(int32_t n, const int32_t* h, const int32_t* J, i
     *out = nullptr;
     if (n < 1 || n > 16384) return fail(SSQA_EINVAL, "n_spins = %d outside [1, 16384]", n);
     if (!h || !J) return fail(SSQA_EINVAL, "h or J is NULL");
-    const CouplingScan sc = scan_couplings(n, h, J, nullptr);
+    // Large problems are narrowed to int8 during the checking pass when J fits one plane, so that a quarter of
+    // the bytes crosses to the device.
+    std::unique_ptr<int8_t[]> j8;
+    if ((long long)n * n >= (1LL << 20)) j8.reset(new (std::nothrow) int8_t[(size_t)n * n]);
+    const CouplingScan sc = scan_couplings(n, h, J, j8.get());
     const ssqa_status st = check_couplings(sc, n, J);
     if (st != SSQA_OK) return st;
-    return create_problem_impl(n, h, J, nullptr, sc, device, out);
+    return create_problem_impl(n, h, J, sc.planes == 1 ? j8.get() : nullptr, sc, device, out);
 }
 
 void ssqa_destroy_problem(ssqa_problem_t p) {
