@@ -289,31 +289,59 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
     const uint32_t tn2 = (uint32_t)x.two_n * 0x00010001u;
     const uint32_t tq2 = (uint32_t)x.two_q * 0x00010001u;
 
+    // With 128-column blocks (one wave per SIMD, 512 registers) the LDS words the epilogue reads are read
+    // ahead of the LDS writes that precede their use: the compiler cannot tell that those writes (the next
+    // bit plane, the energy sums) leave them unchanged, so a read placed after a write is issued there and
+    // waited for at once, with no other wave to absorb the latency.  The energy term's row constants are the
+    // same for every fragment and are read once (8 x 16 bytes per lane), the column table entries of all
+    // fragments next, and the bit-plane and noise words of fragment f + 1 while fragment f is worked on.
+    // Narrower blocks, whose two waves per SIMD cover each other's latency, have no registers to spare for
+    // this and read each word where it is used.
+    constexpr bool kAhead = kNBF == 8;
+    v4i er[8];
+    uint32_t info_f[kNBF];
+    if constexpr (kAhead) {
+#pragma unroll
+        for (int ai = 0; ai < 8; ++ai) er[ai] = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
+#pragma unroll
+        for (int f = 0; f < kNBF; ++f) info_f[f] = x.colinfo[x.coff + 16 * f + ecol];
+    }
+    uint32_t nx_sig = 0, nx_up = 0, nx_dn = 0, nx_noise = 0;
+    auto read_words = [&](const int f) {
+        const int c = x.coff + 16 * f + ecol;
+        if constexpr (!kAhead) info_f[f] = x.colinfo[c];
+        nx_sig = ~x.pl_cur[c * x.cstride + word];
+        if (kUpdate) {
+            nx_up = x.pl_del[(info_f[f] & 0xFFu) * x.cstride + word];
+            if (kMode == 1) nx_dn = x.pl_del[((info_f[f] >> 8) & 0xFFu) * x.cstride + word];
+            nx_noise = x.noise_lds[(x.wave * x.ncols + c) * 4 + eg];
+        }
+    };
+    if constexpr (kAhead) read_words(0);
+
 #pragma unroll
     for (int f = 0; f < kNBF; ++f) {
         const int c = x.coff + 16 * f + ecol;
-        const uint32_t info = x.colinfo[c];
-        const uint32_t nsig = ~x.pl_cur[c * x.cstride + word];
+        if constexpr (!kAhead) read_words(f);
+        const uint32_t info = info_f[f];
+        const uint32_t nsig = nx_sig;
+        uint32_t up_w = nx_up, dn_w = nx_dn, noise_w = nx_noise;
+        if (kAhead && f + 1 < kNBF) read_words(f + 1);
         // four independent partial sums (one per byte position j), so that the energy is not one long chain
         int ep4[4] = {__builtin_popcount(nsig), 0, 0, 0};
-        uint32_t negbits = 0, up_w = 0, dn_w = 0, noise_w = 0;
+        uint32_t negbits = 0;
         v4i* is_ptr = reinterpret_cast<v4i*>(x.is_wg + (size_t)c * x.np + row0);
-        constexpr int kAhead = cnt_ahead<kFp4>();
-        if (kUpdate && f + kAhead < kNBF)
-            load_counters<kFp4>(cnt[f + kAhead], x.is_wg + (size_t)(x.coff + ecol) * x.np + row0, x.np, f + kAhead);
+        constexpr int kCnt = cnt_ahead<kFp4>();
+        if (kUpdate && f + kCnt < kNBF)
+            load_counters<kFp4>(cnt[f + kCnt], x.is_wg + (size_t)(x.coff + ecol) * x.np + row0, x.np, f + kCnt);
         v4i is_lo = cnt[f][0], is_hi = cnt[f][1];
-        if (kUpdate) {
-            up_w = x.pl_del[(info & 0xFFu) * x.cstride + word];
-            if (kMode == 1) dn_w = x.pl_del[((info >> 8) & 0xFFu) * x.cstride + word];
-            noise_w = x.noise_lds[(x.wave * x.ncols + c) * 4 + eg];
-            if (kFast) {
-                up_w ^= x.qflip;
-                dn_w ^= x.qflip;
-            }
+        if (kUpdate && kFast) {
+            up_w ^= x.qflip;
+            dn_w ^= x.qflip;
         }
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
-            const v4i er4 = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
+            const v4i er4 = kAhead ? er[ai] : *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
             uint32_t isw_new = 0;
             int nvs[4] = {0, 0, 0, 0};
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
