@@ -162,6 +162,52 @@ __device__ __forceinline__ void mma_fp4_cols(v4i (&A)[8], v4i& Bc, const uint32_
     }
 }
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// One fp4 (e2m1) 32 x 32 x 64 MFMA, fp32 accumulation, J scaled by 2 and x by 1 as in mfma_fp4.  The 128-column
+// blocks use it: an fp4 MFMA of this shape leaves the SIMD's issue port free for about four VALU instructions
+// of the same wave (a 16 x 16 x 128 one, half its work, for about one), so the operand expansion and the
+// interleaved loads cost the K loop nothing.
+__device__ __forceinline__ v16f mfma_fp4_32(const v4i& a, const v4i& b, const v16f& c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(widen(a), widen(b), c, 4, 4, 0, 128, 0, 127);
+}
+
+// One K step (128) of a 128-row tile on 32 x 32 x 64 MFMAs, kNCB column blocks of 32.  A[kh][rb] is the J
+// operand of row block rb for K half kh, cur[kh][cb] the bit-plane word of column block cb for K half kh.  On
+// entry Bc holds the expanded operand of (kh, cb) = (0, 0); while the four MFMAs of one (kh, cb) run, the next
+// operand is expanded in their shadow (with kNext, after the last one, the next step's first from `next0`).
+// With kReload, A[kh][rb] is refilled from byte offset `next` right behind its last MFMA, half a step earlier
+// for K half 0 than for K half 1.  With kStart the accumulators of K half 0 start from start[rb].
+template <int kNCB, bool kReload, bool kNext, bool kStart>
+__device__ __forceinline__ void mma_fp4_wide(v4i (&A)[2][4], v4i& Bc, const uint32_t (&cur)[2][kNCB], uint32_t next0,
+                                             v16f (&acc)[4][kNCB], const v16f (&start)[4],
+                                             __amdgpu_buffer_rsrc_t rsrc, int voff, int next) {
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+#pragma unroll
+        for (int cb = 0; cb < kNCB; ++cb) {
+            v4i Bn = Bc;
+            if (cb + 1 < kNCB) Bn = expand_operand_fp4(cur[kh][cb + 1]);
+            else if (kh == 0) Bn = expand_operand_fp4(cur[1][0]);
+            else if (kNext) Bn = expand_operand_fp4(next0);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb][cb] = mfma_fp4_32(A[kh][rb], Bc, (kStart && kh == 0) ? start[rb] : acc[rb][cb]);
+                if (kReload && cb == kNCB - 1) A[kh][rb] = load_j(rsrc, voff, next + rb * 2048 + kh * 512);
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then up to two VALU instructions
+                if (kReload && cb == kNCB - 1) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // and one J load
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            Bc = Bn;
+        }
+    }
+}
+
 // The 32 int8 counters of this lane in column fragment f (column 16 f + lane % 16).  With fp4 operands they
 // are read through the caches: the fp4 copy of J leaves room in L2, a one-wave-per-SIMD epilogue has no other
 // wave to cover their latency, and streaming (nontemporal) loads of them measured 3-5 % slower on the whole
@@ -170,6 +216,18 @@ __device__ __forceinline__ void mma_fp4_cols(v4i (&A)[8], v4i& Bc, const uint32_
 template <bool kFp4>
 __device__ __forceinline__ void load_counters(v4i (&c)[2], const int8_t* is_lane, int np, int f) {
     const v4i* src = reinterpret_cast<const v4i*>(is_lane + (size_t)16 * f * np);
+    if constexpr (kFp4) {
+        c[0] = src[0];
+        c[1] = src[1];
+    } else {
+        c[0] = __builtin_nontemporal_load(src);
+        c[1] = __builtin_nontemporal_load(src + 1);
+    }
+}
+
+template <bool kFp4>
+__device__ __forceinline__ void load_counters_at(v4i (&c)[2], const int8_t* p) {
+    const v4i* src = reinterpret_cast<const v4i*>(p);
     if constexpr (kFp4) {
         c[0] = src[0];
         c[1] = src[1];
@@ -257,31 +315,46 @@ __device__ __forceinline__ int agpr_read(int x) {
     return r;
 }
 
-// Fused epilogue of one 128-row tile for the kNBF column fragments of this wave.  Lane (column
-// 16 f + (lane & 15), group g = lane >> 4) owns tile rows 32 g .. 32 g + 31 of fragment f, i.e. one 32-bit
-// word of every bit plane and of the Philox block, and 32 consecutive int8 counters.  With kUpdate the
-// counters and the next bit plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the
-// current state is always accumulated.
+// Accumulator (row offset 4 ai + j of unit u) in the two MFMA output layouts: 16 x 16 tiles (acc[ai][u], unit u
+// = column fragment u) and 32 x 32 tiles (acc[rb][cb], unit u = (rr, cb) = (u / kN, u % kN), whose register
+// 4 i + j holds tile row 64 (i & 1) + 32 (lane / 32) + 8 rb + 4 (i >> 1) + j).  kAgpr reads it out of its AGPR
+// where it is used.
+template <bool kAgpr, int kN>
+__device__ __forceinline__ int acc_value(const v4i (&acc)[8][kN], int u, int ai, int j) {
+    return kAgpr ? agpr_read(acc[ai][u][j]) : acc[ai][u][j];
+}
+template <bool kAgpr, int kN>
+__device__ __forceinline__ int acc_value(const v16i (&acc)[4][kN], int u, int ai, int j) {
+    const int v = acc[ai >> 1][u % kN][4 * (2 * (ai & 1) + u / kN) + j];
+    return kAgpr ? agpr_read(v) : v;
+}
+
+// Fused epilogue of one 128-row tile for the kUnits units of this wave.  A unit is one column and one run of
+// 32 consecutive tile rows of it: with 16 x 16 MFMA tiles (kWide false) unit u is column 16 u + lane % 16 and
+// run lane / 16 (tile rows 32 (lane / 16) ..); with 32 x 32 tiles (kWide) unit u = rr kNCB + cb is column
+// 32 cb + lane % 32 and run 2 rr + lane / 32.  The lane owns one 32-bit word of every bit plane and of the
+// Philox block in each unit, and 32 consecutive int8 counters.  With kUpdate the counters and the next bit
+// plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the current state is always
+// accumulated.
 //
-// Row offset o = 4 a + j of the lane's 32 rows sits in byte j of counter dword a and at bit 8 j + a of the
-// bit-plane words (bitpos), and at bit o of the Philox word.
+// Row offset o = 4 a + j of a run sits in byte j of counter dword a and at bit 8 j + a of the bit-plane words
+// (bitpos), and at bit o of the Philox word.
 //
 // kFast (alpha = 1, and max_t I_0 + 2 n_rnd + 2 max_t |J_perp| (1 + mode) <= 128): the counters of the 4
 // rows of dword a, offset by 128, and their noise and coupling increments 2 n_rnd [r = +1] and
 // 2 |J_perp| [coupled spin agrees with the sign of J_perp] are summed as 4 bytes at once without carries;
 // per row only the field is added and the sum clamped to [-I_0, I_0 - 1] (Eq. 6b with alpha = 1).
 // Otherwise each row's input is assembled in 32 bits and clamped as Eq. 6b states for any alpha.
-template <bool kUpdate, bool kFast, int kMode, int kNBF, bool kFp4>
-__device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&cnt)[kNBF][2],
-                                               const EpilogueCtx& x) {
+template <bool kUpdate, bool kFast, int kMode, int kUnits, bool kFp4, bool kWide = false, class AccT>
+__device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnits][2], const EpilogueCtx& x) {
     // Per-lane addressing is rebuilt here from a laundered lane index, so that none of it stays live (in
     // registers) across the K loop.
     int ln = x.lane;
     asm volatile("" : "+v"(ln));
-    const int ecol = ln & 15;
-    const int eg = ln >> 4;
-    const int word = x.tile * 4 + eg;
-    const int row0 = x.tile * kTileRows + 32 * eg;
+    constexpr int kNCB = kUnits / 2;
+    auto ucol = [&](const int u) { return x.coff + (kWide ? 32 * (u % kNCB) + (ln & 31) : 16 * u + (ln & 15)); };
+    auto urun = [&](const int u) { return kWide ? 2 * (u / kNCB) + (ln >> 5) : (ln >> 4); };
+    auto ucnt = [&](const int u) { return x.is_wg + (size_t)ucol(u) * x.np + x.tile * kTileRows + 32 * urun(u); };
     // clamp bounds of Eq. 6b, shifted by the accumulator's offset (its low byte is zero, so the low byte of a
     // shifted counter is the counter)
     constexpr int kOff = kFp4 ? 0x4B400000 : 0;
@@ -292,56 +365,65 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
     // With 128-column blocks (one wave per SIMD, 512 registers) the LDS words the epilogue reads are read
     // ahead of the LDS writes that precede their use: the compiler cannot tell that those writes (the next
     // bit plane, the energy sums) leave them unchanged, so a read placed after a write is issued there and
-    // waited for at once, with no other wave to absorb the latency.  The energy term's row constants are the
-    // same for every fragment and are read once (8 x 16 bytes per lane), the column table entries of all
-    // fragments next, and the bit-plane and noise words of fragment f + 1 while fragment f is worked on.
-    // Narrower blocks, whose two waves per SIMD cover each other's latency, have no registers to spare for
-    // this and read each word where it is used.
-    constexpr bool kAhead = kNBF == 8;
-    v4i er[8];
-    uint32_t info_f[kNBF];
+    // waited for at once, with no other wave to absorb the latency.  The energy term's row constants of a run
+    // are read once per run (8 x 16 bytes per lane; with 32 x 32 tiles those of the second run during the
+    // last unit of the first), the column table entries of all units next, and the bit-plane and noise words
+    // of unit u + 1 while unit u is worked on.  Narrower blocks, whose two waves per SIMD cover each other's
+    // latency, have no registers to spare for this and read each word where it is used.
+    constexpr bool kAhead = kUnits == 8;
+    v4i er[8], er_next[8];
+    uint32_t info_u[kUnits];
+    auto read_er = [&](v4i (&dst)[8], const int u) {
+#pragma unroll
+        for (int ai = 0; ai < 8; ++ai) dst[ai] = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * urun(u) + 4 * ai);
+    };
     if constexpr (kAhead) {
+        read_er(er, 0);
 #pragma unroll
-        for (int ai = 0; ai < 8; ++ai) er[ai] = *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
-#pragma unroll
-        for (int f = 0; f < kNBF; ++f) info_f[f] = x.colinfo[x.coff + 16 * f + ecol];
+        for (int u = 0; u < kUnits; ++u) info_u[u] = x.colinfo[ucol(u)];
     }
     uint32_t nx_sig = 0, nx_up = 0, nx_dn = 0, nx_noise = 0;
-    auto read_words = [&](const int f) {
-        const int c = x.coff + 16 * f + ecol;
-        if constexpr (!kAhead) info_f[f] = x.colinfo[c];
+    auto read_words = [&](const int u) {
+        const int c = ucol(u);
+        const int word = x.tile * 4 + urun(u);
+        if constexpr (!kAhead) info_u[u] = x.colinfo[c];
         nx_sig = ~x.pl_cur[c * x.cstride + word];
         if (kUpdate) {
-            nx_up = x.pl_del[(info_f[f] & 0xFFu) * x.cstride + word];
-            if (kMode == 1) nx_dn = x.pl_del[((info_f[f] >> 8) & 0xFFu) * x.cstride + word];
-            nx_noise = x.noise_lds[(x.wave * x.ncols + c) * 4 + eg];
+            nx_up = x.pl_del[(info_u[u] & 0xFFu) * x.cstride + word];
+            if (kMode == 1) nx_dn = x.pl_del[((info_u[u] >> 8) & 0xFFu) * x.cstride + word];
+            nx_noise = x.noise_lds[(x.wave * x.ncols + c) * 4 + urun(u)];
         }
     };
     if constexpr (kAhead) read_words(0);
 
 #pragma unroll
-    for (int f = 0; f < kNBF; ++f) {
-        const int c = x.coff + 16 * f + ecol;
-        if constexpr (!kAhead) read_words(f);
-        const uint32_t info = info_f[f];
+    for (int u = 0; u < kUnits; ++u) {
+        const int c = ucol(u);
+        const int word = x.tile * 4 + urun(u);
+        if constexpr (!kAhead) read_words(u);
+        const uint32_t info = info_u[u];
         const uint32_t nsig = nx_sig;
         uint32_t up_w = nx_up, dn_w = nx_dn, noise_w = nx_noise;
-        if (kAhead && f + 1 < kNBF) read_words(f + 1);
+        if (kAhead && u + 1 < kUnits) read_words(u + 1);
+        if (kAhead && kWide && u + 1 == kNCB) read_er(er_next, u + 1);
+        if (kAhead && kWide && u == kNCB) {
+#pragma unroll
+            for (int ai = 0; ai < 8; ++ai) er[ai] = er_next[ai];
+        }
         // four independent partial sums (one per byte position j), so that the energy is not one long chain
         int ep4[4] = {__builtin_popcount(nsig), 0, 0, 0};
         uint32_t negbits = 0;
-        v4i* is_ptr = reinterpret_cast<v4i*>(x.is_wg + (size_t)c * x.np + row0);
+        v4i* is_ptr = reinterpret_cast<v4i*>(ucnt(u));
         constexpr int kCnt = cnt_ahead<kFp4>();
-        if (kUpdate && f + kCnt < kNBF)
-            load_counters<kFp4>(cnt[f + kCnt], x.is_wg + (size_t)(x.coff + ecol) * x.np + row0, x.np, f + kCnt);
-        v4i is_lo = cnt[f][0], is_hi = cnt[f][1];
+        if (kUpdate && u + kCnt < kUnits) load_counters_at<kFp4>(cnt[u + kCnt], ucnt(u + kCnt));
+        v4i is_lo = cnt[u][0], is_hi = cnt[u][1];
         if (kUpdate && kFast) {
             up_w ^= x.qflip;
             dn_w ^= x.qflip;
         }
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
-            const v4i er4 = kAhead ? er[ai] : *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * eg + 4 * ai);
+            const v4i er4 = kAhead ? er[ai] : *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * urun(u) + 4 * ai);
             uint32_t isw_new = 0;
             int nvs[4] = {0, 0, 0, 0};
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
@@ -357,7 +439,7 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
             for (int j = 0; j < 4; ++j) {
                 const int pos = 8 * j + ai;
                 // the counter input without Is and the noise and coupling bytes (plus 0x4B400000 with fp4)
-                const int f2 = kNBF == 8 ? agpr_read(acc[ai][f][j]) : acc[ai][f][j];
+                const int f2 = acc_value<kUnits == 8>(acc, u, ai, j);
                 // energy: (e ^ -1) = -e - 1 for sigma = -1; the -1s are restored by the popcount of nsig
                 ep4[j] = xad_u32(f2 + er4[j], bfe_i((int)nsig, pos, 1), ep4[j]);
                 if (kUpdate) {
@@ -391,9 +473,9 @@ __device__ __forceinline__ void fused_epilogue(const v4i (&acc)[8][kNBF], v4i (&
             __builtin_nontemporal_store(is_hi, is_ptr + 1);
             x.pl_next[c * x.cstride + word] = ~negbits;
         }
-        // Each lane adds its 32 rows' share: the four lanes of a column meet in the LDS atomic, which needs no
-        // lane index (a cross-lane shuffle would need one, and with every register taken the compiler reloads
-        // it from scratch, whose wait then also drains the counter stores just issued).
+        // Each lane adds its 32 rows' share: the lanes of a column meet in the LDS atomic, which needs no lane
+        // index (a cross-lane shuffle would need one, and with every register taken the compiler reloads it
+        // from scratch, whose wait then also drains the counter stores just issued).
         const int ep = (ep4[0] + ep4[1]) + (ep4[2] + ep4[3]);
         if (info >> 31) atomicAdd(&x.e_acc[c], ep);
     }
@@ -833,7 +915,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             // h - adj_c - kAccOffset, so that start + 2 sum_j J_ij x_j + this = 2 h + F (the energy term).
             stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
             const int32_t* rows_w = rowst + wave * 256;
+            // 128-column blocks with fp4 operands take 32 x 32 x 64 MFMAs (kWideT); the rest 16 x 16 ones.
+            constexpr bool kWideT = kFp4 && kNBF == 8;
+            constexpr int kNCB = kF / 2;
             v4i acc[8][kF];
+            v16i accw[4][kNCB];
             // This lane's counters of the tile, fetched during the last K steps for the epilogue.
             v4i cnt[kF][2];
             // Lane-derived addresses are rebuilt per tile from a laundered lane index: held across the
@@ -845,7 +931,80 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             const int tg = tl >> 4;
             int8_t* is_lane = is_wg + (size_t)(tcol + 16 * foff) * np + tile * kTileRows + 32 * tg;
             const int voff = tl * 16;
-            if constexpr (kFp4) {
+            if constexpr (kWideT) {
+                // Field product on the fp4 copy of J (the same layout and exactness argument as below) with
+                // 32 x 32 x 64 MFMAs: per K step of 128, row blocks rb < 4 of 32 rows, column blocks cb < kNCB
+                // of 32 columns and K halves kh < 2.  Lane l loads the 16 bytes of J for operand row p = l % 32
+                // and K half-group l / 32: row p of block rb is the layout's slot p % 16 of fragment
+                // 2 rb + p / 16, so that each load reads two contiguous 512-byte runs, and output register
+                // 4 i + j of the lane lands on tile row 64 (i & 1) + 32 (l / 32) + 8 rb + 4 (i >> 1) + j: two
+                // runs of 32 consecutive rows per lane and column, as the epilogue's units want them.
+                v16f accf[4][kNCB];
+                const int ns = a.prob.kp4 / 128;          // even, >= 4
+                const int jv = ((tl & 31) >> 4) * 1024 + ((tl >> 5) * 16 + (tl & 15)) * 16;
+                const int tile_off = tile * ns * 8 * 1024;
+                // Word 4 s + 2 kh + l / 32 of the lane's column for K step s (past the column's slot for the
+                // last steps when kp4 > np, as below: J is zero there).
+                const uint32_t* bsrc = pl_cur + (16 * foff + (tl & 31)) * cstride + (tl >> 5);
+                v4i A0[2][4], A1[2][4];
+                uint32_t w[2][kNCB], wn[2][kNCB];
+                auto read_words = [&](uint32_t (&dst)[2][kNCB], int s) {
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+                        for (int cb = 0; cb < kNCB; ++cb) dst[kh][cb] = bsrc[32 * cb * cstride + 4 * s + 2 * kh];
+                };
+                auto load_step = [&](v4i (&A)[2][4], int off) {
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb) A[kh][rb] = load_j(j4rsrc, jv, off + rb * 2048 + kh * 512);
+                };
+                load_step(A0, tile_off);
+                load_step(A1, tile_off + 8 * 1024);
+                read_words(w, 0);
+                // The accumulators' starts (register 4 i + j of row block rb: the staged constant of its tile
+                // row), read while the first J fragments are on their way.
+                v16f start[4];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    v4i q[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        q[i] = *reinterpret_cast<const v4i*>(rows_w + 64 * (i & 1) + 32 * (tl >> 5) + 8 * rb + 4 * (i >> 1));
+                    start[rb] = __builtin_bit_cast(v16f, (v16i){q[0][0], q[0][1], q[0][2], q[0][3], q[1][0], q[1][1], q[1][2],
+                                                               q[1][3], q[2][0], q[2][1], q[2][2], q[2][3], q[3][0], q[3][1],
+                                                               q[3][2], q[3][3]});
+                }
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as below
+                v4i Bc = expand_operand_fp4(w[0][0]);
+                read_words(wn, 1);
+                mma_fp4_wide<kNCB, true, true, true>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv, tile_off + 2 * 8 * 1024);
+                read_words(w, 2);
+                mma_fp4_wide<kNCB, true, true, false>(A1, Bc, wn, w[0][0], accf, start, j4rsrc, jv, tile_off + 3 * 8 * 1024);
+                for (int s = 2; s < ns - 2; s += 2) {
+                    read_words(wn, s + 1);
+                    mma_fp4_wide<kNCB, true, true, false>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv,
+                                                          tile_off + (s + 2) * 8 * 1024);
+                    read_words(w, s + 2);
+                    mma_fp4_wide<kNCB, true, true, false>(A1, Bc, wn, w[0][0], accf, start, j4rsrc, jv,
+                                                          tile_off + (s + 3) * 8 * 1024);
+                }
+                read_words(wn, ns - 1);
+                mma_fp4_wide<kNCB, false, true, false>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv, 0);
+                if (more) rowv_next = fetch_rows(a.prob, next_tile);
+                // the counters of the epilogue's first units (columns 32 u + l % 32, run l / 32)
+                {
+                    const int8_t* p0 = is_wg + (size_t)(16 * foff + (tl & 31)) * np + tile * kTileRows + 32 * (tl >> 5);
+#pragma unroll
+                    for (int u = 0; u < kF && u < cnt_ahead<kFp4>(); ++u) load_counters_at<kFp4>(cnt[u], p0 + (size_t)32 * u * np);
+                }
+                mma_fp4_wide<kNCB, false, false, false>(A1, Bc, wn, 0u, accf, start, j4rsrc, jv, 0);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < kNCB; ++cb) accw[rb][cb] = __builtin_bit_cast(v16i, accf[rb][cb]);
+            } else if constexpr (kFp4) {
                 // Field product on the fp4 copy of J: K steps of 128 with J scaled by 2, fp32 accumulators that
                 // start from the staged per-row constant (1.5 * 2^23 plus an integer).  Every partial sum is
                 // 1.5 * 2^23 plus an integer of magnitude below 2^22, so it is exact in any summation order and
@@ -867,6 +1026,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 load_fragments(A0, j4rsrc, voff, tile_off);
                 load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
                 read_words(w, 0);
+                // With 128-column blocks (512 registers) the staged accumulator starts of all eight row blocks are
+                // read here, while the first J fragments are on their way: read one row block at a time in the
+                // first K step, each read waits out the LDS latency on its own, with no other wave on the SIMD.
+                // Narrower blocks have no registers to spare for them and read each where it is used.
+                v4i start4[8];
+                if constexpr (kNBF == 8) {
+#pragma unroll
+                    for (int ai = 0; ai < 8; ++ai) start4[ai] = *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai);
+                }
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in the int8 loop
                 // ns >= 4.  The J loads in flight at the head of the steady loop are the same, in the same order, on
                 // entry and around the loop (A0 of step s + 2, then A1 of step s + 3), and every path into the loop
@@ -881,7 +1049,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                     read_words(wn, 1);
 #pragma unroll
                     for (int ai = 0; ai < 8; ++ai) {
-                        const v4f start = __builtin_bit_cast(v4f, *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
+                        const v4f start = __builtin_bit_cast(
+                            v4f, kNBF == 8 ? start4[ai] : *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
 #pragma unroll
                         for (int f = 0; f < kF; ++f) accf[ai][f] = mfma_fp4(A0[ai], B[f], start);
                         A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
@@ -1005,9 +1174,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                fused_epilogue<true, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
+                if constexpr (kWideT) fused_epilogue<true, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
+                else fused_epilogue<true, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             } else {
-                fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
+                if constexpr (kWideT) fused_epilogue<false, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
+                else fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             }
         
         };
