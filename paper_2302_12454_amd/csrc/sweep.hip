@@ -165,10 +165,10 @@ __device__ __forceinline__ void mma_fp4_cols(v4i (&A)[8], v4i& Bc, const uint32_
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-// One fp4 (e2m1) 32 x 32 x 64 MFMA, fp32 accumulation, J scaled by 2 and x by 1 as in mfma_fp4.  The 128-column
-// blocks use it: an fp4 MFMA of this shape leaves the SIMD's issue port free for about four VALU instructions
-// of the same wave (a 16 x 16 x 128 one, half its work, for about one), so the operand expansion and the
-// interleaved loads cost the K loop nothing.
+// One fp4 (e2m1) 32 x 32 x 64 MFMA, fp32 accumulation, J scaled by 2 and x by 1 as in mfma_fp4.  The 128- and
+// 64-column blocks use it: an fp4 MFMA of this shape leaves the SIMD's issue port free for a few simple VALU
+// instructions of the same wave (a 16 x 16 x 128 one, half its work, for about one), so the operand expansion
+// and the interleaved loads cost the K loop nothing.
 __device__ __forceinline__ v16f mfma_fp4_32(const v4i& a, const v4i& b, const v16f& c) {
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(widen(a), widen(b), c, 4, 4, 0, 128, 0, 127);
 }
@@ -915,8 +915,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             // h - adj_c - kAccOffset, so that start + 2 sum_j J_ij x_j + this = 2 h + F (the energy term).
             stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
             const int32_t* rows_w = rowst + wave * 256;
-            // 128-column blocks with fp4 operands take 32 x 32 x 64 MFMAs (kWideT); the rest 16 x 16 ones.
-            constexpr bool kWideT = kFp4 && kNBF == 8;
+            // 128- and 64-column blocks with fp4 operands take 32 x 32 x 64 MFMAs (kWideT); the rest 16 x 16 ones
+            // (32-column fp4 blocks and int8 operands).
+            constexpr bool kWideT = kFp4 && (kNBF == 8 || kNBF == 4);
             constexpr int kNCB = kF / 2;
             v4i acc[8][kF];
             v16i accw[4][kNCB];
