@@ -316,7 +316,7 @@ __device__ __forceinline__ int agpr_read(int x) {
 }
 
 // Accumulator (row offset 4 ai + j of unit u) in the two MFMA output layouts: 16 x 16 tiles (acc[ai][u], unit u
-// = column fragment u) and 32 x 32 tiles (acc[rb][cb], unit u = (rr, cb) = (u / kN, u % kN), whose register
+// = column fragment u) and 32 x 32 tiles (acc[rb][cb], unit u = (cb, rr) = (u / 2, u % 2), whose register
 // 4 i + j holds tile row 64 (i & 1) + 32 (lane / 32) + 8 rb + 4 (i >> 1) + j).  kAgpr reads it out of its AGPR
 // where it is used.
 template <bool kAgpr, int kN>
@@ -325,14 +325,16 @@ __device__ __forceinline__ int acc_value(const v4i (&acc)[8][kN], int u, int ai,
 }
 template <bool kAgpr, int kN>
 __device__ __forceinline__ int acc_value(const v16i (&acc)[4][kN], int u, int ai, int j) {
-    const int v = acc[ai >> 1][u % kN][4 * (2 * (ai & 1) + u / kN) + j];
+    const int v = acc[ai >> 1][u >> 1][4 * (2 * (ai & 1) + (u & 1)) + j];
     return kAgpr ? agpr_read(v) : v;
 }
 
 // Fused epilogue of one 128-row tile for the kUnits units of this wave.  A unit is one column and one run of
 // 32 consecutive tile rows of it: with 16 x 16 MFMA tiles (kWide false) unit u is column 16 u + lane % 16 and
-// run lane / 16 (tile rows 32 (lane / 16) ..); with 32 x 32 tiles (kWide) unit u = rr kNCB + cb is column
-// 32 cb + lane % 32 and run 2 rr + lane / 32.  The lane owns one 32-bit word of every bit plane and of the
+// run lane / 16 (tile rows 32 (lane / 16) ..); with 32 x 32 tiles (kWide) unit u = 2 cb + rr is column
+// 32 cb + lane % 32 and run 2 rr + lane / 32, so that the two units of a column, whose counters share the
+// tile's 128-byte line, follow each other (their stores then meet in L2 and leave as whole lines; with the
+// column's halves kNCB units apart they left partly as halves: 28 % more HBM write traffic).  The lane owns one 32-bit word of every bit plane and of the
 // Philox block in each unit, and 32 consecutive int8 counters.  With kUpdate the counters and the next bit
 // plane are written (Eq. 6a-c); the energy sum_i sigma_i (2 h_i + F_i) of the current state is always
 // accumulated.
@@ -352,8 +354,8 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
     int ln = x.lane;
     asm volatile("" : "+v"(ln));
     constexpr int kNCB = kUnits / 2;
-    auto ucol = [&](const int u) { return x.coff + (kWide ? 32 * (u % kNCB) + (ln & 31) : 16 * u + (ln & 15)); };
-    auto urun = [&](const int u) { return kWide ? 2 * (u / kNCB) + (ln >> 5) : (ln >> 4); };
+    auto ucol = [&](const int u) { return x.coff + (kWide ? 32 * (u >> 1) + (ln & 31) : 16 * u + (ln & 15)); };
+    auto urun = [&](const int u) { return kWide ? 2 * (u & 1) + (ln >> 5) : (ln >> 4); };
     auto ucnt = [&](const int u) { return x.is_wg + (size_t)ucol(u) * x.np + x.tile * kTileRows + 32 * urun(u); };
     // clamp bounds of Eq. 6b, shifted by the accumulator's offset (its low byte is zero, so the low byte of a
     // shifted counter is the counter)
@@ -365,13 +367,13 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
     // With 128-column blocks (one wave per SIMD, 512 registers) the LDS words the epilogue reads are read
     // ahead of the LDS writes that precede their use: the compiler cannot tell that those writes (the next
     // bit plane, the energy sums) leave them unchanged, so a read placed after a write is issued there and
-    // waited for at once, with no other wave to absorb the latency.  The energy term's row constants of a run
-    // are read once per run (8 x 16 bytes per lane; with 32 x 32 tiles those of the second run during the
-    // last unit of the first), the column table entries of all units next, and the bit-plane and noise words
-    // of unit u + 1 while unit u is worked on.  Narrower blocks, whose two waves per SIMD cover each other's
+    // waited for at once, with no other wave to absorb the latency.  The energy term's row constants of the
+    // lane's runs are read once (8 x 16 bytes per run and lane; 32 x 32 tiles alternate between two runs), the
+    // column table entries of all units next, and the bit-plane and noise words of unit u + 1 while unit u is
+    // worked on.  Narrower blocks, whose two waves per SIMD cover each other's
     // latency, have no registers to spare for this and read each word where it is used.
     constexpr bool kAhead = kUnits == 8;
-    v4i er[8], er_next[8];
+    v4i er[8], er1[8];
     uint32_t info_u[kUnits];
     auto read_er = [&](v4i (&dst)[8], const int u) {
 #pragma unroll
@@ -379,6 +381,7 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
     };
     if constexpr (kAhead) {
         read_er(er, 0);
+        if constexpr (kWide) read_er(er1, 1);
 #pragma unroll
         for (int u = 0; u < kUnits; ++u) info_u[u] = x.colinfo[ucol(u)];
     }
@@ -405,11 +408,6 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
         const uint32_t nsig = nx_sig;
         uint32_t up_w = nx_up, dn_w = nx_dn, noise_w = nx_noise;
         if (kAhead && u + 1 < kUnits) read_words(u + 1);
-        if (kAhead && kWide && u + 1 == kNCB) read_er(er_next, u + 1);
-        if (kAhead && kWide && u == kNCB) {
-#pragma unroll
-            for (int ai = 0; ai < 8; ++ai) er[ai] = er_next[ai];
-        }
         // four independent partial sums (one per byte position j), so that the energy is not one long chain
         int ep4[4] = {__builtin_popcount(nsig), 0, 0, 0};
         uint32_t negbits = 0;
@@ -423,7 +421,8 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
         }
 #pragma unroll
         for (int ai = 0; ai < 8; ++ai) {
-            const v4i er4 = kAhead ? er[ai] : *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * urun(u) + 4 * ai);
+            const v4i er4 = kAhead ? ((kWide && (u & 1)) ? er1[ai] : er[ai])
+                                   : *reinterpret_cast<const v4i*>(x.rows + 128 + 32 * urun(u) + 4 * ai);
             uint32_t isw_new = 0;
             int nvs[4] = {0, 0, 0, 0};
             const int isw = kUpdate ? (ai < 4 ? is_lo[ai] : is_hi[ai - 4]) : 0;
@@ -994,11 +993,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 read_words(wn, ns - 1);
                 mma_fp4_wide<kNCB, false, true, false>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv, 0);
                 if (more) rowv_next = fetch_rows(a.prob, next_tile);
-                // the counters of the epilogue's first units (columns 32 u + l % 32, run l / 32)
+                // the counters of the epilogue's first units (unit u: column 32 (u / 2) + l % 32, run 2 (u % 2) + l / 32)
                 {
                     const int8_t* p0 = is_wg + (size_t)(16 * foff + (tl & 31)) * np + tile * kTileRows + 32 * (tl >> 5);
 #pragma unroll
-                    for (int u = 0; u < kF && u < cnt_ahead<kFp4>(); ++u) load_counters_at<kFp4>(cnt[u], p0 + (size_t)32 * u * np);
+                    for (int u = 0; u < kF && u < cnt_ahead<kFp4>(); ++u)
+                        load_counters_at<kFp4>(cnt[u], p0 + (size_t)32 * (u >> 1) * np + 64 * (u & 1));
                 }
                 mma_fp4_wide<kNCB, false, false, false>(A1, Bc, wn, 0u, accf, start, j4rsrc, jv, 0);
 #pragma unroll
