@@ -211,8 +211,11 @@ __device__ __forceinline__ void mma_fp4_wide(v4i (&A)[2][4], v4i& Bc, const uint
 // The 32 int8 counters of this lane in column fragment f (column 16 f + lane % 16).  With fp4 operands they
 // are read through the caches: the fp4 copy of J leaves room in L2, a one-wave-per-SIMD epilogue has no other
 // wave to cover their latency, and streaming (nontemporal) loads of them measured 3-5 % slower on the whole
-// anneal.  With int8 operands J alone overflows L2, and cached counter loads evict it (3 % slower), so they
-// stream.  The epilogue writes them back with streaming stores, which nothing reads before the next cycle.
+// anneal.  With int8 operands on 16 x 16 tiles J alone overflows L2, and cached counter loads evict it (3 %
+// slower), so they stream.  On 32 x 32 tiles a unit reads half of a 128-byte counter line and the next unit
+// the other half; streamed, each half fetched the line again and the int8 epilogue took twice as long, so
+// there they go through the caches with either operand type.  The epilogue writes the counters back with
+// streaming stores, which nothing reads before the next cycle.
 template <bool kFp4>
 __device__ __forceinline__ void load_counters(v4i (&c)[2], const int8_t* is_lane, int np, int f) {
     const v4i* src = reinterpret_cast<const v4i*>(is_lane + (size_t)16 * f * np);
@@ -222,6 +225,38 @@ __device__ __forceinline__ void load_counters(v4i (&c)[2], const int8_t* is_lane
     } else {
         c[0] = __builtin_nontemporal_load(src);
         c[1] = __builtin_nontemporal_load(src + 1);
+    }
+}
+
+// One K step (64) of a 128-row tile on int8 32 x 32 x 32 MFMAs (single-plane J), as mma_fp4_wide: A[kh][rb] is
+// the J operand of row block rb for K half kh (32), cur[kh][cb] the bit-plane word of column block cb for that
+// half, whose lane half `bsh` holds the lane's 16 K values.
+template <int kNCB, bool kReload, bool kNext>
+__device__ __forceinline__ void mma_i8_wide(v4i (&A)[2][4], v4i& Bc, const uint32_t (&cur)[2][kNCB], uint32_t next0,
+                                            int bsh, v16i (&acc)[4][kNCB], __amdgpu_buffer_rsrc_t rsrc, int voff,
+                                            int next) {
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+#pragma unroll
+        for (int cb = 0; cb < kNCB; ++cb) {
+            v4i Bn = Bc;
+            if (cb + 1 < kNCB) Bn = expand_operand(cur[kh][cb + 1] >> bsh);
+            else if (kh == 0) Bn = expand_operand(cur[1][0] >> bsh);
+            else if (kNext) Bn = expand_operand(next0 >> bsh);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[kh][rb], Bc, acc[rb][cb], 0, 0, 0);
+                if (kReload && cb == kNCB - 1) A[kh][rb] = load_j(rsrc, voff, next + rb * 2048 + kh * 512);
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then up to two VALU instructions
+                if (kReload && cb == kNCB - 1) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // and one J load
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            Bc = Bn;
+        }
     }
 }
 
@@ -237,11 +272,11 @@ __device__ __forceinline__ void load_counters_at(v4i (&c)[2], const int8_t* p) {
     }
 }
 
-// Counters are fetched cnt_ahead fragments ahead of their use: those of fragments 0 .. cnt_ahead - 1 during
-// the last K steps, that of fragment f + cnt_ahead while the epilogue works on fragment f (two with fp4
-// operands, where the cached loads made the deeper prefetch pay; one with int8).
-template <bool kFp4>
-constexpr int cnt_ahead() { return kFp4 ? 2 : 1; }
+// Counters are fetched cnt_ahead fragments (units) ahead of their use: those of units 0 .. cnt_ahead - 1
+// during the last K steps, that of unit u + cnt_ahead while the epilogue works on unit u (two with cached
+// loads, where the deeper prefetch paid; one with streaming loads).  kCached: fp4 operands, or 32 x 32 tiles.
+template <bool kCached>
+constexpr int cnt_ahead() { return kCached ? 2 : 1; }
 
 template <int kNBF, bool kFp4>
 __device__ __forceinline__ void prefetch_counters(v4i (&cnt)[kNBF][2], const int8_t* is_lane, int np) {
@@ -412,8 +447,10 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
         int ep4[4] = {__builtin_popcount(nsig), 0, 0, 0};
         uint32_t negbits = 0;
         v4i* is_ptr = reinterpret_cast<v4i*>(ucnt(u));
-        constexpr int kCnt = cnt_ahead<kFp4>();
-        if (kUpdate && u + kCnt < kUnits) load_counters_at<kFp4>(cnt[u + kCnt], ucnt(u + kCnt));
+        // With 32 x 32 tiles a unit's counters are half of a 128-byte line whose other half the next unit reads:
+        // those go through the caches with either operand type, two units ahead.
+        constexpr int kCnt = cnt_ahead<kFp4 || kWide>();
+        if (kUpdate && u + kCnt < kUnits) load_counters_at<kFp4 || kWide>(cnt[u + kCnt], ucnt(u + kCnt));
         v4i is_lo = cnt[u][0], is_hi = cnt[u][1];
         if (kUpdate && kFast) {
             up_w ^= x.qflip;
@@ -917,6 +954,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             // 128- and 64-column blocks with fp4 operands take 32 x 32 x 64 MFMAs (kWideT); the rest 16 x 16 ones
             // (32-column fp4 blocks and int8 operands).
             constexpr bool kWideT = kFp4 && (kNBF == 8 || kNBF == 4);
+            // 128-column blocks with int8 operands (single-plane J) take int8 32 x 32 x 32 MFMAs (kWideI), in the
+            // same output layout.
+            constexpr bool kWideI = !kFp4 && kNBF == 8;
             constexpr int kNCB = kF / 2;
             v4i acc[8][kF];
             v16i accw[4][kNCB];
@@ -997,8 +1037,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 {
                     const int8_t* p0 = is_wg + (size_t)(16 * foff + (tl & 31)) * np + tile * kTileRows + 32 * (tl >> 5);
 #pragma unroll
-                    for (int u = 0; u < kF && u < cnt_ahead<kFp4>(); ++u)
-                        load_counters_at<kFp4>(cnt[u], p0 + (size_t)32 * (u >> 1) * np + 64 * (u & 1));
+                    for (int u = 0; u < kF && u < cnt_ahead<true>(); ++u)
+                        load_counters_at<true>(cnt[u], p0 + (size_t)32 * (u >> 1) * np + 64 * (u & 1));
                 }
                 mma_fp4_wide<kNCB, false, false, false>(A1, Bc, wn, 0u, accf, start, j4rsrc, jv, 0);
 #pragma unroll
@@ -1079,6 +1119,64 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 for (int ai = 0; ai < 8; ++ai)
 #pragma unroll
                     for (int f = 0; f < kF; ++f) acc[ai][f] = __builtin_bit_cast(v4i, accf[ai][f]);
+            } else if constexpr (kWideI) {
+                // Field product on int8 J (one plane) with 32 x 32 x 32 MFMAs: per K step of 64, row blocks rb < 4,
+                // column blocks cb < kNCB and K halves kh < 2 of 32.  Lane l loads the 16 bytes of J for operand row
+                // p = l % 32 and K group 2 kh + l / 32 (slot p % 16 of fragment 2 rb + p / 16 of the int8 layout, as
+                // on the fp4 path), and the operand 2 x of its 16 K values from half l / 32 of bit-plane word 2 s + kh.
+                // The accumulators start from the staged constants (register 4 i + j of row block rb: tile row
+                // 64 (i & 1) + 32 (l / 32) + 8 rb + 4 (i >> 1) + j) and end as the counter input v.
+                const int jv = ((tl & 31) >> 4) * 1024 + ((tl >> 5) * 16 + (tl & 15)) * 16;
+                const int tile_off = tile * nsteps * 8 * 1024;
+                const uint32_t* bsrc = pl_cur + (16 * foff + (tl & 31)) * cstride;
+                const int bsh = 4 * (tl >> 5);
+                v4i A0[2][4], A1[2][4];
+                uint32_t w[2][kNCB], wn[2][kNCB];
+                auto read_words = [&](uint32_t (&dst)[2][kNCB], int s) {
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+                        for (int cb = 0; cb < kNCB; ++cb) dst[kh][cb] = bsrc[32 * cb * cstride + 2 * s + kh];
+                };
+                auto load_step = [&](v4i (&A)[2][4], int off) {
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb) A[kh][rb] = load_j(jrsrc, jv, off + rb * 2048 + kh * 512);
+                };
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    v4i q[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        q[i] = *reinterpret_cast<const v4i*>(rows_w + 64 * (i & 1) + 32 * (tl >> 5) + 8 * rb + 4 * (i >> 1));
+                    const v16i st = (v16i){q[0][0], q[0][1], q[0][2], q[0][3], q[1][0], q[1][1], q[1][2], q[1][3],
+                                           q[2][0], q[2][1], q[2][2], q[2][3], q[3][0], q[3][1], q[3][2], q[3][3]};
+#pragma unroll
+                    for (int cb = 0; cb < kNCB; ++cb) accw[rb][cb] = st;
+                }
+                load_step(A0, tile_off);
+                load_step(A1, tile_off + 8 * 1024);
+                read_words(w, 0);
+                // Drain the first loads here, as below.
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                v4i Bc = expand_operand(w[0][0] >> bsh);
+                for (int s = 0; s < nsteps - 2; s += 2) {
+                    read_words(wn, s + 1);
+                    mma_i8_wide<kNCB, true, true>(A0, Bc, w, wn[0][0], bsh, accw, jrsrc, jv, tile_off + (s + 2) * 8 * 1024);
+                    read_words(w, s + 2);
+                    mma_i8_wide<kNCB, true, true>(A1, Bc, wn, w[0][0], bsh, accw, jrsrc, jv, tile_off + (s + 3) * 8 * 1024);
+                }
+                read_words(wn, nsteps - 1);
+                mma_i8_wide<kNCB, false, true>(A0, Bc, w, wn[0][0], bsh, accw, jrsrc, jv, 0);
+                if (more) rowv_next = fetch_rows(a.prob, next_tile);
+                {
+                    const int8_t* p0 = is_wg + (size_t)(16 * foff + (tl & 31)) * np + tile * kTileRows + 32 * (tl >> 5);
+#pragma unroll
+                    for (int u = 0; u < kF && u < cnt_ahead<true>(); ++u)
+                        load_counters_at<true>(cnt[u], p0 + (size_t)32 * (u >> 1) * np + 64 * (u & 1));
+                }
+                mma_i8_wide<kNCB, false, false>(A1, Bc, wn, 0u, bsh, accw, jrsrc, jv, 0);
             } else {
                 // Output slot (ai, r = col16) of every fragment is tile row 32 (r / 4) + 4 ai + r % 4, so lane
                 // group g ends up with rows 32 g .. 32 g + 31.  The operand is 2 x, so the accumulators collect
@@ -1175,10 +1273,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if constexpr (kWideT) fused_epilogue<true, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
+                if constexpr (kWideT || kWideI) fused_epilogue<true, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
                 else fused_epilogue<true, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             } else {
-                if constexpr (kWideT) fused_epilogue<false, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
+                if constexpr (kWideT || kWideI) fused_epilogue<false, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
                 else fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             }
         
