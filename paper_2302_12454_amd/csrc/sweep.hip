@@ -951,8 +951,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             // h - adj_c - kAccOffset, so that start + 2 sum_j J_ij x_j + this = 2 h + F (the energy term).
             stage_rows(rowst + wave * 256, rowv_next, row_add_h, row_add_e);
             const int32_t* rows_w = rowst + wave * 256;
-            // 128- and 64-column blocks with fp4 operands take 32 x 32 x 64 MFMAs (kWideT); the rest 16 x 16 ones
-            // (32-column fp4 blocks and int8 operands).
+            // 128- and 64-column blocks with fp4 operands take 32 x 32 x 64 MFMAs (kWideT); 32-column fp4 blocks and
+            // int8 operands on 64 and 32 columns take 16 x 16 ones.
             constexpr bool kWideT = kFp4 && (kNBF == 8 || kNBF == 4);
             // 128-column blocks with int8 operands (single-plane J) take int8 32 x 32 x 32 MFMAs (kWideI), in the
             // same output layout.
