@@ -144,6 +144,15 @@ typedef struct ssqa_anneal_params {
     int32_t stop_cycle;        /* 0 or cycles: run to the end (including the energy of sigma(SC));
                                   t1 in (start_cycle, cycles): stop after cycle t1 - 1            */
     const ssqa_anneal_state* resume;   /* required when start_cycle > 0, else ignored            */
+    int32_t split_rows;        /* ssqa_anneal only: the row-split form (each trial's rows spread over
+                                  row groups of workgroups, one launch per cycle; Sec. 3.2's update of
+                                  all N R spins per cycle is unchanged): 0 = automatic (taken from 1280
+                                  padded rows when the trials fill at most 16 column blocks of 32 or 64
+                                  columns), -1 = never, k > 0 = from k padded rows on.  Only for fresh
+                                  runs to the end (start_cycle = 0, stop_cycle = 0 or cycles, no
+                                  checkpoint) on blocks of at most 64 columns (block_columns 0, 32 or
+                                  64); other runs, ssqa_anneal_noalloc, batches and served requests
+                                  ignore it.  A scheduling choice only: results do not depend on it */
 } ssqa_anneal_params;
 
 typedef struct ssqa_anneal_outputs {

@@ -40,6 +40,7 @@ class AnnealParams(ctypes.Structure):
         ("start_cycle", ctypes.c_int32),
         ("stop_cycle", ctypes.c_int32),
         ("resume", ctypes.POINTER(AnnealState)),
+        ("split_rows", ctypes.c_int32),
     ]
 
 

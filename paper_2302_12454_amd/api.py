@@ -170,9 +170,11 @@ def ssqa_anneal(problem: Problem, *, replicas: int, trials: int, cycles: int, jp
                 noise_amp: int, delay: int, seed: int, coupling_mode: int = 0, target=None,
                 trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0, block_columns: int = 0,
                 operand_format: int = 0, stream=None, out: AnnealResult | None = None,
-                stop_cycle: int = 0, resume: "AnnealState | None" = None, checkpoint: bool = False) -> AnnealResult:
+                stop_cycle: int = 0, resume: "AnnealState | None" = None, checkpoint: bool = False,
+                split_rows: int = 0) -> AnnealResult:
     """ssqa_anneal on torch-owned device outputs.  Asynchronous on ``stream`` (default: the
-    current stream).  ``out`` may carry preallocated outputs of the right shapes.
+    current stream).  ``out`` may carry preallocated outputs of the right shapes.  ``split_rows`` picks
+    the row-split form (0: automatic, -1: never, k > 0: from k padded rows on; see ssqa.h).
 
     Checkpoint / resume: ``checkpoint=True`` returns the state after the last cycle run (``stop_cycle``,
     or all ``cycles``) in ``result.checkpoint``; ``resume=state`` continues from it (pass the interrupted
@@ -185,7 +187,7 @@ def ssqa_anneal_noalloc(problem: Problem, *, replicas: int, trials: int, cycles:
                         trace: bool = False, final_is: bool = False, cycles_per_launch: int = 0,
                         block_columns: int = 0, operand_format: int = 0, stream=None,
                         out: AnnealResult | None = None, stop_cycle: int = 0, resume: "AnnealState | None" = None,
-                        checkpoint: bool = False) -> AnnealResult:
+                        checkpoint: bool = False, split_rows: int = 0) -> AnnealResult:
     """ssqa_anneal_noalloc: ssqa_anneal with the anneal's device state in the library's fixed per-device
     scratch (no device allocation by the library).  Same arguments and results as ``ssqa_anneal``; the
     outputs are still torch tensors unless ``out`` brings them."""
@@ -194,7 +196,7 @@ def ssqa_anneal_noalloc(problem: Problem, *, replicas: int, trials: int, cycles:
 
 def _anneal_call(fn: str, *, problem, replicas, trials, cycles, jperp, i0, alpha, noise_amp, delay, seed,
                  coupling_mode, target, trace, final_is, cycles_per_launch, block_columns, operand_format,
-                 stream, out, stop_cycle, resume, checkpoint) -> AnnealResult:
+                 stream, out, stop_cycle, resume, checkpoint, split_rows=0) -> AnnealResult:
     import torch
     lib = _lib.load()
     if out is None:
@@ -212,6 +214,7 @@ def _anneal_call(fn: str, *, problem, replicas, trials, cycles, jperp, i0, alpha
                       cycles_per_launch=cycles_per_launch, block_columns=block_columns,
                       operand_format=operand_format)
     p.stop_cycle = int(stop_cycle)
+    p.split_rows = int(split_rows)
     rs = _state_struct(resume)
     if resume is not None:
         p.start_cycle = int(resume.cycle)

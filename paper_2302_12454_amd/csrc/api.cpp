@@ -322,6 +322,91 @@ AnnealSizes anneal_sizes(const ssqa_problem* prob, const ssqa_anneal_params* pa)
     return z;
 }
 
+// Padded rows from which an automatic plain anneal considers the row-split form.
+// Automatic row-split form: from this many padded rows, for anneals of at most kSplitMaxBlocks column blocks.
+// The persistent form gives each workgroup whole trials, so every workgroup streams all of J through its CU
+// once per cycle, whatever the number of workgroups; an anneal of few trials (SSA's R = 1, say) is then bound
+// by one CU's load rate.  The row-split form spreads each trial's rows over row groups of workgroups at the
+// price of one launch per cycle and sigma's exchange through device memory; on one MI355X it was measured
+// faster from N = 1225 (1280 padded rows) for 4 to 16 column blocks, slower at N = 625 and for 50 blocks of
+// 64 columns below N = 2025.
+constexpr int kSplitPlainRows = 1280;
+constexpr int kSplitMaxBlocks = 16;
+
+// Column-block width of the row-split form for a plain anneal (ssqa_anneal_params.split_rows), or 0 for the
+// persistent form.  Blocks hold whole trials: 32 columns while that gives few enough blocks (a narrower block
+// shortens each wave's work per cycle), else 64.
+static int plain_split_columns(const ssqa_problem* prob, const ssqa_anneal_params* pa, int t0, int t1,
+                               bool checkpoint, bool workspace) {
+    if (pa->split_rows < 0 || workspace || checkpoint || t0 != 0 || t1 != pa->cycles) return 0;
+    const int np = prob->dev.np, R = pa->replicas, T = pa->trials;
+    auto fits = [&](int nb) { return R <= nb && sweep_lds_bytes(np, pa->delay, nb) <= 160 * 1024; };
+    auto blocks = [&](int nb) { return (T + nb / R - 1) / (nb / R); };
+    int nb = pa->block_columns;
+    if (nb == 0) nb = fits(32) && (blocks(32) <= kSplitMaxBlocks || !fits(64)) ? 32 : 64;
+    if (nb > 64 || !fits(nb)) return 0;
+    if (pa->split_rows > 0) return np >= pa->split_rows ? nb : 0;
+    return np >= kSplitPlainRows && blocks(nb) <= kSplitMaxBlocks ? nb : 0;
+}
+
+// The row-split form of a fresh anneal run to the end: whole trials per column block (nb / R each), the
+// block's rows in row groups of kGroupTiles tiles, one sweep_split_kernel launch per cycle (the launch
+// boundary is the cycle's barrier), sigma's ring of d + 2 bit planes and the energy sums in device memory.
+static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
+                               int nb, bool fp4, hipStream_t stream) {
+    const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
+    const int np = prob->dev.np, tpw = nb / R;
+    const int n_cb = (T + tpw - 1) / tpw;
+    // The fewest row tiles per group (1, 2 or 4) that keep the row groups within two per CU: a group's
+    // workgroup reads its tiles' J rows every cycle, so smaller groups shorten the cycle while CUs are idle.
+    const int xcds = device_xcd_count(prob->device), cus = device_cu_count(prob->device);
+    int group_tiles = 1;
+    while (group_tiles < kGroupTiles && (long long)n_cb * split_groups(np, xcds, group_tiles) > 2LL * cus)
+        group_tiles *= 2;
+    const int n_groups = split_groups(np, xcds, group_tiles);
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t o_sched = 0;
+    const size_t o_is = align((size_t)2 * std::max(SC, 1) * 4);
+    const size_t o_ring = o_is + align((size_t)n_cb * nb * np);
+    const size_t o_esum = o_ring + align((size_t)(pa->delay + 2) * n_cb * nb * (np / 32) * 4);
+    const size_t esum_bytes = (size_t)2 * n_cb * nb * 4;
+    const size_t o_item = o_esum + align(esum_bytes);
+    const size_t total = o_item + sizeof(SweepArgs);
+    retain_pool_memory(prob->device);
+    void* mem = nullptr;
+    hipError_t e = hipMallocAsync(&mem, total, stream);
+    if (e != hipSuccess) return e;
+    char* base = static_cast<char*>(mem);
+    int32_t* d_sched = reinterpret_cast<int32_t*>(base + o_sched);
+    SweepArgs a = make_args(prob, pa, out, d_sched, d_sched + std::max(SC, 1), reinterpret_cast<int8_t*>(base + o_is),
+                            nullptr, nb, tpw, fp4 ? 1 : 0);
+    a.n_cb = n_cb;
+    a.n_groups = n_groups;
+    a.group_tiles = group_tiles;
+    a.ring = reinterpret_cast<uint32_t*>(base + o_ring);
+    a.e_sum = reinterpret_cast<int32_t*>(base + o_esum);
+    a.final_pass = 1;
+    SweepArgs* d_args = reinterpret_cast<SweepArgs*>(base + o_item);
+    {
+        // schedules and arguments through pinned staging (no host wait); the energy slots start at zero
+        const void* srcs[3] = {pa->jperp, pa->i0, &a};
+        const size_t sizes[3] = {(size_t)SC * 4, (size_t)SC * 4, sizeof(SweepArgs)};
+        if (SC > 0) e = staged_upload(prob->device, d_sched, srcs, sizes, 2, stream);
+        if (e == hipSuccess) e = staged_upload(prob->device, d_args, srcs + 2, sizes + 2, 1, stream);
+        if (e == hipSuccess) e = hipMemsetAsync(a.e_sum, 0, esum_bytes, stream);
+    }
+    if (e == hipSuccess) e = launch_sweep_split(d_args, a, 0, kSplitInit, stream);
+    for (int t = 0; e == hipSuccess && t < SC; ++t)
+        e = launch_sweep_split(d_args, a, t, kSplitRun | kSplitUpdate | (t > 0 ? kSplitClose : 0), stream);
+    // the energy of sigma(SC), then the close of its cycle
+    if (e == hipSuccess) e = launch_sweep_split(d_args, a, SC, kSplitRun | (SC > 0 ? kSplitClose : 0), stream);
+    if (e == hipSuccess) e = launch_sweep_split(d_args, a, SC + 1, kSplitClose, stream);
+    if (e == hipSuccess && out->final_is)
+        e = launch_copy_final_is(a.is_state, np, prob->dev.n, R, T, tpw, nb, out->final_is, stream);
+    (void)hipFreeAsync(mem, stream);
+    return e;
+}
+
 ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
                         hipStream_t stream, const AnnealWorkspace* ws) {
     if (!prob || !pa || !out) return fail(SSQA_EINVAL, "NULL problem, params or outputs");
@@ -344,6 +429,12 @@ ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, 
     const AnnealSizes z = anneal_sizes(prob, pa);
     const int nb = z.layout.nb, tpw = z.layout.tpw, n_wg = z.layout.n_wg;
     const int np = prob->dev.np;
+    if (const int split_nb = plain_split_columns(prob, pa, t0, t1, ckpt != nullptr, ws != nullptr)) {
+        const hipError_t se = anneal_split(prob, pa, out, split_nb, z.layout.fp4, stream);
+        if (se != hipSuccess)
+            return se == hipErrorOutOfMemory ? fail(SSQA_ENOMEM, "device allocation failed") : hip_fail(se, "anneal");
+        return SSQA_OK;
+    }
 
     int8_t* is_state = nullptr;
     uint32_t* hist = nullptr;

@@ -101,10 +101,19 @@ struct SweepArgs {
     int32_t* e_sum;         // [2][n_cb * nb]: sum_i sigma_i (2 h_i + F_i) of cycle t in slot t & 1
 };
 
-// Flags of one sweep_split_kernel launch at cycle t.
+// Row tiles per group of the row-split form (at most one per wave), and the groups of a block: enough to cover
+// the tiles, rounded up to a multiple of the XCD count so that a row group's copies in every block share an XCD.
+constexpr int kGroupTiles = 4;
+inline int split_groups(int np, int xcds, int group_tiles = kGroupTiles) {
+    const int g = (np / kTileRows + group_tiles - 1) / group_tiles;
+    return (g + xcds - 1) / xcds * xcds;
+}
+
+// Flags of one sweep_split_kernel launch at cycle t; its grid is n_cb x n_groups row-group workgroups (init,
+// run), then n_cb closing workgroups (close).
 constexpr int kSplitInit = 1;    // sigma(0) and Is(0) of the group's rows, best and first hit reset (t = 0)
-constexpr int kSplitClose = 2;   // first reduce cycle t - 1's energies to the trace, best and first hit
-constexpr int kSplitRun = 4;     // then the field product, energy and (with kSplitUpdate) the update of cycle t
+constexpr int kSplitClose = 2;   // reduce cycle t - 1's energies to the trace, best and first hit
+constexpr int kSplitRun = 4;     // the field product, energy and (with kSplitUpdate) the update of cycle t
 constexpr int kSplitUpdate = 8;
 
 // Launchers (sweep.hip).  Return hipSuccess or the launch error.
@@ -301,6 +310,7 @@ ssqa_status anneal_impl(const ssqa_problem* prob, const ssqa_anneal_params* pa, 
 hipError_t staged_upload(int device, void* dst, const void* const* srcs, const size_t* sizes, int count,
                          hipStream_t stream);
 int device_cu_count(int device);
+int device_xcd_count(int device);
 // Keep freed stream-ordered allocations in the device pool.
 void retain_pool_memory(int device);
 

@@ -79,14 +79,6 @@ int split_floor(int split_rows) { return split_rows == 0 ? 4096 : split_rows < 0
 // Whether a request takes the row-split form: enough rows, and a block narrower than 128 columns.
 bool takes_split(int np, int nb, int split_rows) { return np >= split_floor(split_rows) && nb <= 64; }
 
-// Row tiles per group of the row-split form (one per wave), and the groups of a block: enough to cover the
-// tiles, rounded up to a multiple of the XCD count so that a row group's copies in every block share an XCD.
-constexpr int kGroupTiles = 4;
-int split_groups(int np, int xcds) {
-    const int g = (np / kTileRows + kGroupTiles - 1) / kGroupTiles;
-    return (g + xcds - 1) / xcds * xcds;
-}
-
 // Device bytes of one admitted request: int8 planes, the fp4 copy of J (counted whether or not the
 // problem turns out to be fp4-exact), row vectors, counters, bit-plane history (or, in the row-split form,
 // the bit-plane ring and energy sums), outputs, schedules.

@@ -761,39 +761,40 @@ __device__ void split_init_state(const SweepArgs& a, const int cb, const int g) 
 
 // Cycle t of column block cb, once every row group has added its energy sums (the previous launch): each
 // replica's H_p (trace), the per-trial minimum and first hit in device memory; the sums are cleared for cycle
-// t + 2.  Wave w takes trials w, w + kWaves, ...; lane k reads replica k (and k + 64, ...).
+// t + 2.  One wave, lane c on column c = lb R + k (trial lb, replica k; a block has at most 64 columns): every
+// load is issued at once, and each trial's minimum is folded onto its replica-0 lane by a segmented reduction.
 template <int kNB>
 __device__ void split_close_cycle(const SweepArgs& a, const int cb, const int t) {
-    const int ln = __lane_id();
-    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    const int R = a.R, b0 = cb * a.tpw;
+    static_assert(kNB <= 64, "the row-split form takes blocks of at most 64 columns");
+    if (threadIdx.x >= 64) return;
+    const int c = threadIdx.x;
+    const int R = a.R;
+    const int lb = c / R, k = c - lb * R;
+    const int b = cb * a.tpw + lb;
+    const bool real = c < a.cols_wg && b < a.T;
+    const bool head = real && k == 0;
     int32_t* sums = a.e_sum + (size_t)(t & 1) * a.n_cb * kNB + (size_t)cb * kNB;
-    for (int lb = wv; lb < a.tpw; lb += kWaves) {
-        const int b = b0 + lb;
-        int m = INT32_MAX;
-        for (int k = ln; k < R; k += 64) {
-            const int c = lb * R + k;
-            const int e = -sums[c] / 2;
-            if (b < a.T && a.trace) a.trace[(size_t)t * a.T * R + (size_t)b * R + k] = e;
-            m = e < m ? e : m;
-            sums[c] = 0;
+    const long long best = head ? a.best[b] : 0;
+    const int hit = head ? a.first_hit[b] : 0;
+    int m = INT32_MAX;
+    if (c < kNB) {
+        const int e = -sums[c] / 2;
+        sums[c] = 0;
+        if (real) {
+            m = e;
+            if (a.trace) a.trace[((size_t)t * a.T + b) * R + k] = e;
         }
-        int o = __builtin_amdgcn_ds_swizzle(m, (1 << 10) | 0x1F);
-        m = o < m ? o : m;
-        o = __builtin_amdgcn_ds_swizzle(m, (2 << 10) | 0x1F);
-        m = o < m ? o : m;
-        o = __builtin_amdgcn_ds_swizzle(m, (4 << 10) | 0x1F);
-        m = o < m ? o : m;
-        o = __builtin_amdgcn_ds_swizzle(m, (8 << 10) | 0x1F);
-        m = o < m ? o : m;
-        o = __builtin_amdgcn_ds_swizzle(m, (16 << 10) | 0x1F);
-        m = o < m ? o : m;
-        const int lo = __builtin_amdgcn_readlane(m, 0), hi = __builtin_amdgcn_readlane(m, 32);
-        const long long mm = lo < hi ? lo : hi;
-        if (ln == 0 && b < a.T) {
-            if (mm < a.best[b]) a.best[b] = mm;
-            if (a.first_hit[b] < 0 && a.target != INT64_MIN && mm == a.target) a.first_hit[b] = t;
-        }
+    }
+    // Lane c takes the minimum of lanes c .. c + 2 off - 1 of its trial; lanes past the trial's last replica
+    // (k + off >= R) are never read, so the reads stay below lane a.cols_wg <= 64.
+    for (int off = 1; off < R; off <<= 1) {
+        const int o = __shfl_down(m, off, 64);
+        if (k + off < R) m = o < m ? o : m;
+    }
+    if (head) {
+        const long long mm = m;
+        if (mm < best) a.best[b] = mm;
+        if (hit < 0 && a.target != INT64_MIN && mm == a.target) a.first_hit[b] = t;
     }
 }
 
@@ -1334,15 +1335,19 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_split_kernel(const SweepArg
         split_init_state<16 * kNBF>(a, cb, g);
         return;
     }
-    if ((flags & kSplitClose) && g == 0) split_close_cycle<16 * kNBF>(a, cb, t - 1);
-    if (flags & kSplitRun) {
-        const bool update = (flags & kSplitUpdate) != 0;
-        a.t_begin = t;
-        a.t_end = update ? t + 1 : t;
-        a.final_pass = update ? 0 : 1;
-        a.save_hist = 0;
-        sweep_block<kFast, kMode, kNBF, kFp4, true>(a, cb, g);
+    // The close of cycle t - 1 runs in workgroups of its own (after the row groups with kSplitRun, alone
+    // without), beside the row groups that add cycle t's sums to the other slot.
+    const int n_run = (flags & kSplitRun) ? a.n_cb * a.n_groups : 0;
+    if ((int)blockIdx.x >= n_run) {
+        if (flags & kSplitClose) split_close_cycle<16 * kNBF>(a, blockIdx.x - n_run, t - 1);
+        return;
     }
+    const bool update = (flags & kSplitUpdate) != 0;
+    a.t_begin = t;
+    a.t_end = update ? t + 1 : t;
+    a.final_pass = update ? 0 : 1;
+    a.save_hist = 0;
+    sweep_block<kFast, kMode, kNBF, kFp4, true>(a, cb, g);
 }
 
 // Many anneals in one launch: work item blockIdx.x is (anneal index << 16 | column block), listed by the
@@ -1630,7 +1635,11 @@ hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int 
     const hipError_t ce = configure_sweep_kernels();
     if (ce != hipSuccess) return ce;
     const size_t lds = (flags & kSplitRun) ? sweep_lds_bytes(host.prob.np, host.delay, host.nb) : 0;
-    const dim3 grid(host.n_cb * host.n_groups), block(kThreads);
+    // row groups (init, run), then one closing workgroup per column block (close)
+    const int n_rows = (flags & (kSplitInit | kSplitRun)) ? host.n_cb * host.n_groups : 0;
+    const int n_close = (flags & kSplitClose) && !(flags & kSplitInit) ? host.n_cb : 0;
+    if (n_rows + n_close == 0) return hipSuccess;
+    const dim3 grid(n_rows + n_close), block(kThreads);
     switch (sweep_variant(host.fast != 0, host.mode, host.nb, host.fp4 != 0)) {
 #define SSQA_LAUNCH_SPLIT(v, al, mo, nbf, f4)                                                                   \
     case v:                                                                                                   \

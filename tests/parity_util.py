@@ -26,13 +26,13 @@ def gi_case(n: int, graph_seed: int, scale: int = 12):
 
 
 def run_gpu(prob, *, replicas, trials, cycles, q, i0, alpha, noise, delay, seed, mode=0, target=None,
-            cycles_per_launch=0, trace=True, final_is=True, block_columns=0, operand_format=0):
+            cycles_per_launch=0, trace=True, final_is=True, block_columns=0, operand_format=0, split_rows=0):
     import torch
     import paper_2302_12454_amd as lib
     res = lib.ssqa_anneal(prob, replicas=replicas, trials=trials, cycles=cycles, jperp=q, i0=i0, alpha=alpha,
                           noise_amp=noise, delay=delay, seed=seed, coupling_mode=mode, target=target,
                           trace=trace, final_is=final_is, cycles_per_launch=cycles_per_launch,
-                          block_columns=block_columns, operand_format=operand_format)
+                          block_columns=block_columns, operand_format=operand_format, split_rows=split_rows)
     torch.cuda.synchronize()
     return {
         "best": res.best_energy.cpu().numpy(),
