@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-int8", action="store_true", help="skip the int8-operand timing of the main anneal")
     ap.add_argument("--int8-steps", type=int, default=2, help="timed anneals with int8 operands")
     ap.add_argument("--no-served", action="store_true", help="skip the compact served figure")
+    ap.add_argument("--table4-sizes", type=int, nargs="*", default=[5, 10, 20, 25, 35, 45, 50],
+                    help="graph sizes n (N = n^2) of the table4 workload")
     ap.add_argument("--cpu-sample-cycles", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (scale for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -359,7 +361,7 @@ def table4_workload(args):
             return None
         return t * math.log(0.01) / math.log(1.0 - p)
 
-    for n in (5, 10, 20, 25, 35, 45, 50):
+    for n in args.table4_sizes:
         pair = random_gi_pair(n, 0.5, n)
         h12, J12, e12 = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, 12)
         h4, J4, e4 = lib.ssqa_gi_to_ising(pair.a1, pair.a2, 1, 1, 4)
