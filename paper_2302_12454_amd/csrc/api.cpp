@@ -364,6 +364,12 @@ static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_param
     while (group_tiles < kGroupTiles && (long long)n_cb * split_groups(np, xcds, group_tiles) > 2LL * cus)
         group_tiles *= 2;
     const int n_groups = split_groups(np, xcds, group_tiles);
+    // Groups of one tile leave three of a workgroup's four waves idle, and one wave alone streams the tile's J
+    // rows at the rate its few loads in flight allow: with 32-column blocks the four waves then share the
+    // tile's K steps (at least four each), when their partial sums fit in LDS beside the bit planes.
+    const int k_steps = fp4 ? prob->dev.kp4 / 128 : np / kStepK;
+    const bool split_k = group_tiles == 1 && nb == 32 && k_steps >= 16 &&
+                         sweep_lds_bytes(np, pa->delay, nb) + split_k_lds_bytes(nb) <= 160 * 1024;
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t o_sched = 0;
     const size_t o_is = align((size_t)2 * std::max(SC, 1) * 4);
@@ -383,6 +389,7 @@ static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_param
     a.n_cb = n_cb;
     a.n_groups = n_groups;
     a.group_tiles = group_tiles;
+    a.split_k = split_k ? 4 : 1;
     a.ring = reinterpret_cast<uint32_t*>(base + o_ring);
     a.e_sum = reinterpret_cast<int32_t*>(base + o_esum);
     a.final_pass = 1;
@@ -395,12 +402,13 @@ static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_param
         if (e == hipSuccess) e = staged_upload(prob->device, d_args, srcs + 2, sizes + 2, 1, stream);
         if (e == hipSuccess) e = hipMemsetAsync(a.e_sum, 0, esum_bytes, stream);
     }
-    if (e == hipSuccess) e = launch_sweep_split(d_args, a, 0, kSplitInit, stream);
+    const int32_t *jp = pa->jperp, *ip = pa->i0;
+    if (e == hipSuccess) e = launch_sweep_split(d_args, a, 0, kSplitInit, jp, ip, stream);
     for (int t = 0; e == hipSuccess && t < SC; ++t)
-        e = launch_sweep_split(d_args, a, t, kSplitRun | kSplitUpdate | (t > 0 ? kSplitClose : 0), stream);
+        e = launch_sweep_split(d_args, a, t, kSplitRun | kSplitUpdate | (t > 0 ? kSplitClose : 0), jp, ip, stream);
     // the energy of sigma(SC), then the close of its cycle
-    if (e == hipSuccess) e = launch_sweep_split(d_args, a, SC, kSplitRun | (SC > 0 ? kSplitClose : 0), stream);
-    if (e == hipSuccess) e = launch_sweep_split(d_args, a, SC + 1, kSplitClose, stream);
+    if (e == hipSuccess) e = launch_sweep_split(d_args, a, SC, kSplitRun | (SC > 0 ? kSplitClose : 0), jp, ip, stream);
+    if (e == hipSuccess) e = launch_sweep_split(d_args, a, SC + 1, kSplitClose, jp, ip, stream);
     if (e == hipSuccess && out->final_is)
         e = launch_copy_final_is(a.is_state, np, prob->dev.n, R, T, tpw, nb, out->final_is, stream);
     (void)hipFreeAsync(mem, stream);

@@ -96,6 +96,9 @@ struct SweepArgs {
     // and the per-column energy sums live in device memory between launches.
     int32_t n_groups;       // row groups per column block
     int32_t group_tiles;    // row tiles per group
+    int32_t split_k;        // 4: groups of one tile of a 32-column block, whose K steps the workgroup's four waves
+                            // share; else 0 or 1
+    int32_t split_q, split_i0;   // J_perp(t) and I_0(t) of the launch's cycle (set by the kernel from its arguments)
     int32_t n_cb;           // column blocks
     uint32_t* ring;         // [d + 2][n_cb][nb][np / 32]: sigma(t) in ring slot t % (d + 2), spread bit order
     int32_t* e_sum;         // [2][n_cb * nb]: sum_i sigma_i (2 h_i + F_i) of cycle t in slot t & 1
@@ -108,6 +111,10 @@ inline int split_groups(int np, int xcds, int group_tiles = kGroupTiles) {
     const int g = (np / kTileRows + group_tiles - 1) / group_tiles;
     return (g + xcds - 1) / xcds * xcds;
 }
+
+// LDS of a row-split launch with split_k = 4 beyond sweep_lds_bytes: three waves' partial accumulators
+// (2 nb 32-bit words per lane) for the fourth to add.
+inline size_t split_k_lds_bytes(int nb) { return (size_t)3 * 64 * 2 * nb * 4; }
 
 // Flags of one sweep_split_kernel launch at cycle t; its grid is n_cb x n_groups row-group workgroups (init,
 // run), then n_cb closing workgroups (close).
@@ -136,7 +143,10 @@ int variant_columns(int variant);
 hipError_t launch_sweep(const SweepArgs& args, int n_wg, hipStream_t stream);
 // One launch of the row-split sweep (item: device copy of the anneal's arguments; grid n_cb * n_groups; kSplit*
 // flags) for a variant with 32 or 64 columns per workgroup.
-hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int t, int flags, hipStream_t stream);
+// The cycle's schedule entries come from the host copies jperp[t] and i0[t] (read with kSplitUpdate only) and
+// travel as launch arguments, so that no launch waits on a device read of them.
+hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int t, int flags, const int32_t* jperp,
+                              const int32_t* i0, hipStream_t stream);
 // items: device array of anneals; work: device list of (item << 16 | column block), n_work entries, all of
 // one kernel variant; the LDS size is taken for the largest padded N and delay among them.
 hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int n_work, int max_np, int max_delay,

@@ -407,17 +407,18 @@ ssqa_status ssqa_server_step(ssqa_server_t s, void* hip_stream, int32_t* active_
             }
             const SweepArgs& a = s->items[i];
             const int c0 = a.t_begin, c1 = a.t_end;
-            if (c0 == 0) SSQA_HIP(launch_sweep_split(r->d_args, a, 0, kSplitInit, side), "split init");
+            const int32_t *jp = r->jperp.data(), *ip = r->i0.data();
+            if (c0 == 0) SSQA_HIP(launch_sweep_split(r->d_args, a, 0, kSplitInit, jp, ip, side), "split init");
             for (int t = c0; t < c1; ++t)
                 SSQA_HIP(launch_sweep_split(r->d_args, a, t, kSplitRun | kSplitUpdate | (t > c0 ? kSplitClose : 0),
-                                            side), "split cycle");
+                                            jp, ip, side), "split cycle");
             int last = c1 - 1;
             if (a.final_pass) {   // the energy of sigma(SC)
-                SSQA_HIP(launch_sweep_split(r->d_args, a, c1, kSplitRun | (c1 > c0 ? kSplitClose : 0), side),
+                SSQA_HIP(launch_sweep_split(r->d_args, a, c1, kSplitRun | (c1 > c0 ? kSplitClose : 0), jp, ip, side),
                          "split final");
                 last = c1;
             }
-            if (last >= c0) SSQA_HIP(launch_sweep_split(r->d_args, a, last + 1, kSplitClose, side), "split close");
+            if (last >= c0) SSQA_HIP(launch_sweep_split(r->d_args, a, last + 1, kSplitClose, jp, ip, side), "split close");
         }
         for (int k = 0; k < used; ++k) SSQA_HIP(hipEventRecord(s->join[k], s->side[k]), "join");
     }

@@ -712,6 +712,17 @@ __device__ __forceinline__ TileRange group_tiles(const SweepArgs& a, int g) {
     return TileRange{lo, min(lo + a.group_tiles, ntiles)};
 }
 
+// K steps [lo, hi) of wave `wave` when the four waves of a row-split workgroup share one tile: the ns steps
+// (ns even) in pairs, as evenly as they go, wave 0 taking the last share (its range ends the product, so its
+// counter prefetch in the last steps precedes the epilogue it runs).  Every share has at least two pairs when
+// ns >= 16.
+__device__ __forceinline__ TileRange k_share(int ns, int wave) {
+    const int pairs = ns / 2, idx = kWaves - 1 - wave;
+    const int base = pairs / kWaves, extra = pairs % kWaves;
+    const int lo = 2 * (idx * base + min(idx, extra));
+    return TileRange{lo, lo + 2 * (base + (idx < extra ? 1 : 0))};
+}
+
 // sigma(0) and Is(0) of group g's rows of column block cb from the random stream (tag 0), into the ring slots
 // of sigma(0) and sigma(-s), s = 1..d; group 0 also resets the block's best energies and first hits.
 template <int kNB>
@@ -819,10 +830,29 @@ __device__ __forceinline__ void split_block_init(const SweepArgs& a, const int c
                        ((uint32_t)valid << 31);
     }
     const int p_cur = t % npl;
-    const uint32_t* src = a.ring + ((size_t)p_cur * a.n_cb + cb) * kNB * words;
-    for (int u = tid; u < kNB * words; u += kThreads) {
-        const int c = u / words;
-        L.planes[p_cur * plane_words + c * cstride + (u - c * words)] = src[u];
+    // sigma(t) of the whole block: 16-byte loads (a column's np / 32 words are a multiple of 4), four per
+    // thread issued before any is stored, so that a block of up to 4096 rows arrives in one memory latency
+    // instead of one per 256 words.
+    const uint4* src = reinterpret_cast<const uint4*>(a.ring + ((size_t)p_cur * a.n_cb + cb) * kNB * words);
+    const int n4 = kNB * words / 4;
+    constexpr int kBatch = 4;
+    for (int u0 = tid; u0 < n4; u0 += kBatch * kThreads) {
+        uint4 v[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            if (u0 + i * kThreads < n4) v[i] = src[u0 + i * kThreads];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int u = u0 + i * kThreads;
+            if (u < n4) {
+                const int c = 4 * u / words;
+                uint32_t* dst = L.planes + p_cur * plane_words + c * cstride + (4 * u - c * words);
+                dst[0] = v[i].x;
+                dst[1] = v[i].y;
+                dst[2] = v[i].z;
+                dst[3] = v[i].w;
+            }
+        }
     }
     if (a.delay > 0) {
         const int p_del = (t - a.delay + npl) % npl;
@@ -886,6 +916,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
     uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
     int32_t* rowst = reinterpret_cast<int32_t*>(colinfo + kNB);      // [kWaves][256]
+    v4i* red = reinterpret_cast<v4i*>(rowst + kWaves * 256);          // [kWaves - 1][kNB / 2][64] (split_k = 4)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -898,6 +929,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
     const BlockLds L{planes, npl, plane_words, cstride, e_acc, hit_l, best_l, colinfo};
     // Row tiles of this workgroup: all of them, or the group's range in the row-split form.
     const TileRange tr = kSplit ? group_tiles(a, group) : TileRange{0, ntiles};
+    // The row-split form fetches its first tile's row vectors ahead of the block state, so that they are on
+    // their way while sigma arrives from device memory.
+    v4i rowv_first{};
+    if constexpr (kSplit) {
+        const int ft = (kNBF == 2 && a.split_k == 4) ? tr.lo : tr.lo + wave;
+        rowv_first = fetch_rows(a.prob, ft < tr.hi ? ft : ntiles - 1);
+    }
     if constexpr (kSplit) split_block_init<kNB>(a, wg, tr, L);
     else block_init<kNB>(a, wg, L);
 
@@ -916,8 +954,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
         const int p_cur = t % npl;
         const int p_next = (t + 1) % npl;
         const int p_del = (t - a.delay + npl) % npl;
-        const int q = update ? a.jperp[t] : 0;
-        const int i0 = update ? a.i0[t] : 0;
+        const int q = update ? (kSplit ? a.split_q : a.jperp[t]) : 0;
+        const int i0 = update ? (kSplit ? a.split_i0 : a.i0[t]) : 0;
         // Counter input (Eq. 6a, with sigma = 2 x - 1 and F = 2 sum_j J_ij x_j - rowsum):
         //   s = Is + 2 sum_j J_ij x_j + (h - rowsum) - n_rnd - q (1 + mode) + 2 n_rnd [r = +1]
         //       + 2 q [sigma_up = +1] (+ 2 q [sigma_dn = +1] in mode 1).
@@ -972,6 +1010,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             const int tg = tl >> 4;
             int8_t* is_lane = is_wg + (size_t)(tcol + 16 * foff) * np + tile * kTileRows + 32 * tg;
             const int voff = tl * 16;
+            // A row-split group of one tile with split_k = 4 (32-column blocks, which have the registers to spare):
+            // the four waves share its K steps (k_share); wave 0 starts from the staged constants, adds the
+            // others' partial sums and alone runs the epilogue.
+            const bool share = kSplit && kNBF == 2 && a.split_k == 4;
+            const bool lead = !share || wave == 0;
             if constexpr (kWideT) {
                 // Field product on the fp4 copy of J (the same layout and exactness argument as below) with
                 // 32 x 32 x 64 MFMAs: per K step of 128, row blocks rb < 4 of 32 rows, column blocks cb < kNCB
@@ -982,6 +1025,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 // runs of 32 consecutive rows per lane and column, as the epilogue's units want them.
                 v16f accf[4][kNCB];
                 const int ns = a.prob.kp4 / 128;          // even, >= 4
+                const TileRange kr = share ? k_share(ns, wave) : TileRange{0, ns};
                 const int jv = ((tl & 31) >> 4) * 1024 + ((tl >> 5) * 16 + (tl & 15)) * 16;
                 const int tile_off = tile * ns * 8 * 1024;
                 // Word 4 s + 2 kh + l / 32 of the lane's column for K step s (past the column's slot for the
@@ -1001,9 +1045,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
 #pragma unroll
                         for (int rb = 0; rb < 4; ++rb) A[kh][rb] = load_j(j4rsrc, jv, off + rb * 2048 + kh * 512);
                 };
-                load_step(A0, tile_off);
-                load_step(A1, tile_off + 8 * 1024);
-                read_words(w, 0);
+                load_step(A0, tile_off + kr.lo * 8 * 1024);
+                load_step(A1, tile_off + (kr.lo + 1) * 8 * 1024);
+                read_words(w, kr.lo);
                 // The accumulators' starts (register 4 i + j of row block rb: the staged constant of its tile
                 // row), read while the first J fragments are on their way.
                 v16f start[4];
@@ -1016,14 +1060,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                     start[rb] = __builtin_bit_cast(v16f, (v16i){q[0][0], q[0][1], q[0][2], q[0][3], q[1][0], q[1][1], q[1][2],
                                                                q[1][3], q[2][0], q[2][1], q[2][2], q[2][3], q[3][0], q[3][1],
                                                                q[3][2], q[3][3]});
+                    if (!lead) start[rb] = v16f{};
                 }
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as below
                 v4i Bc = expand_operand_fp4(w[0][0]);
-                read_words(wn, 1);
-                mma_fp4_wide<kNCB, true, true, true>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv, tile_off + 2 * 8 * 1024);
-                read_words(w, 2);
-                mma_fp4_wide<kNCB, true, true, false>(A1, Bc, wn, w[0][0], accf, start, j4rsrc, jv, tile_off + 3 * 8 * 1024);
-                for (int s = 2; s < ns - 2; s += 2) {
+                read_words(wn, kr.lo + 1);
+                mma_fp4_wide<kNCB, true, true, true>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv,
+                                                     tile_off + (kr.lo + 2) * 8 * 1024);
+                read_words(w, kr.lo + 2);
+                mma_fp4_wide<kNCB, true, true, false>(A1, Bc, wn, w[0][0], accf, start, j4rsrc, jv,
+                                                      tile_off + (kr.lo + 3) * 8 * 1024);
+                for (int s = kr.lo + 2; s < kr.hi - 2; s += 2) {
                     read_words(wn, s + 1);
                     mma_fp4_wide<kNCB, true, true, false>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv,
                                                           tile_off + (s + 2) * 8 * 1024);
@@ -1031,11 +1078,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                     mma_fp4_wide<kNCB, true, true, false>(A1, Bc, wn, w[0][0], accf, start, j4rsrc, jv,
                                                           tile_off + (s + 3) * 8 * 1024);
                 }
-                read_words(wn, ns - 1);
+                read_words(wn, kr.hi - 1);
                 mma_fp4_wide<kNCB, false, true, false>(A0, Bc, w, wn[0][0], accf, start, j4rsrc, jv, 0);
                 if (more) rowv_next = fetch_rows(a.prob, next_tile);
                 // the counters of the epilogue's first units (unit u: column 32 (u / 2) + l % 32, run 2 (u % 2) + l / 32)
-                {
+                if (lead) {
                     const int8_t* p0 = is_wg + (size_t)(16 * foff + (tl & 31)) * np + tile * kTileRows + 32 * (tl >> 5);
 #pragma unroll
                     for (int u = 0; u < kF && u < cnt_ahead<true>(); ++u)
@@ -1053,6 +1100,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 // its bits are 0x4B400000 plus that integer.
                 v4f accf[8][kF];
                 const int ns = a.prob.kp4 / 128;          // even, >= 4
+                const TileRange kr = share ? k_share(ns, wave) : TileRange{0, ns};
                 // Word 4 s + g of the lane's column for K step s.  When kp4 > np the last steps read up to
                 // (kp4 - np) / 32 - 1 words past the column's slot (into the next column, or past the last
                 // plane into the noise area): J is zero for those K, so the bits read there do not matter.
@@ -1065,9 +1113,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
 #pragma unroll
                     for (int f = 0; f < kF; ++f) dst[f] = bsrc[16 * f * cstride + 4 * s];
                 };
-                load_fragments(A0, j4rsrc, voff, tile_off);
-                load_fragments(A1, j4rsrc, voff, tile_off + 8 * 1024);
-                read_words(w, 0);
+                load_fragments(A0, j4rsrc, voff, tile_off + kr.lo * 8 * 1024);
+                load_fragments(A1, j4rsrc, voff, tile_off + (kr.lo + 1) * 8 * 1024);
+                read_words(w, kr.lo);
                 // With 128-column blocks (512 registers) the staged accumulator starts of all eight row blocks are
                 // read here, while the first J fragments are on their way: read one row block at a time in the
                 // first K step, each read waits out the LDS latency on its own, with no other wave on the SIMD.
@@ -1088,22 +1136,23 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                     v4i B[kF];
 #pragma unroll
                     for (int f = 0; f < kF; ++f) B[f] = expand_operand_fp4(w[f]);
-                    read_words(wn, 1);
+                    read_words(wn, kr.lo + 1);
 #pragma unroll
                     for (int ai = 0; ai < 8; ++ai) {
-                        const v4f start = __builtin_bit_cast(
+                        v4f start = __builtin_bit_cast(
                             v4f, kNBF == 8 ? start4[ai] : *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai));
+                        if (!lead) start = v4f{};
 #pragma unroll
                         for (int f = 0; f < kF; ++f) accf[ai][f] = mfma_fp4(A0[ai], B[f], start);
-                        A0[ai] = load_j(j4rsrc, voff, tile_off + 2 * 8 * 1024 + ai * 1024);
+                        A0[ai] = load_j(j4rsrc, voff, tile_off + (kr.lo + 2) * 8 * 1024 + ai * 1024);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     Bc = expand_operand_fp4(wn[0]);
                 }
-                read_words(w, 2);
-                mma_fp4_cols<kF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + 3 * 8 * 1024);
+                read_words(w, kr.lo + 2);
+                mma_fp4_cols<kF, true, true>(A1, Bc, wn, w[0], accf, j4rsrc, voff, tile_off + (kr.lo + 3) * 8 * 1024);
                 // Steady state: each step reloads the A buffer it consumed with the fragments two steps ahead.
-                for (int s = 2; s < ns - 2; s += 2) {
+                for (int s = kr.lo + 2; s < kr.hi - 2; s += 2) {
                     read_words(wn, s + 1);
                     mma_fp4_cols<kF, true, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, tile_off + (s + 2) * 8 * 1024);
                     read_words(w, s + 2);
@@ -1111,10 +1160,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 }
                 // The last two steps: no J left to fetch; the next tile's row vectors and the epilogue's counters
                 // are fetched instead.
-                read_words(wn, ns - 1);
+                read_words(wn, kr.hi - 1);
                 mma_fp4_cols<kF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
                 if (more) rowv_next = fetch_rows(a.prob, next_tile);
-                prefetch_counters<kF, kFp4>(cnt, is_lane, np);
+                if (lead) prefetch_counters<kF, kFp4>(cnt, is_lane, np);
                 mma_fp4_cols<kF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
@@ -1193,10 +1242,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 // The accumulators start from the staged constants (for a single plane; zero when several planes
                 // follow), and each later pass scales the running sum by 256 (exact Horner evaluation over the
                 // planes), the last one adding the start.  Setting them takes the moves a zero start took before.
+                const TileRange kr = share ? k_share(nsteps, wave) : TileRange{0, nsteps};
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai) {
                     v4i st = *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai);
-                    if (P != 1) st = v4i{0, 0, 0, 0};
+                    if (P != 1 || !lead) st = v4i{0, 0, 0, 0};
 #pragma unroll
                     for (int f = 0; f < kF; ++f) acc[ai][f] = st;
                 }
@@ -1205,7 +1255,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
 #pragma unroll
                         for (int ai = 0; ai < 8; ++ai) {
                             v4i st = *reinterpret_cast<const v4i*>(rows_w + 32 * tg + 4 * ai);
-                            if (p != 0) st = v4i{0, 0, 0, 0};
+                            if (p != 0 || !lead) st = v4i{0, 0, 0, 0};
 #pragma unroll
                             for (int f = 0; f < kF; ++f) acc[ai][f] = acc[ai][f] * 256 + st;
                         }
@@ -1215,28 +1265,75 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                     // loads of step s + 2 refill it right behind the MFMAs that read it.
                     const int tile_off = p * np * np + tile * nsteps * 8 * 1024;
                     v4i A0[8], A1[8];
-                    load_fragments(A0, jrsrc, voff, tile_off);
-                    load_fragments(A1, jrsrc, voff, tile_off + 8 * 1024);
-                    read_words(w, 0);
+                    load_fragments(A0, jrsrc, voff, tile_off + kr.lo * 8 * 1024);
+                    load_fragments(A1, jrsrc, voff, tile_off + (kr.lo + 1) * 8 * 1024);
+                    read_words(w, kr.lo);
                     // Drain the first loads here: at the loop head the loads in flight are then exactly the ones
                     // the previous steps issued in fragment order, so each MFMA group waits for its own fragment.
                     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
                     v4i Bc = expand_operand(w[0] >> bsh);
-                    int s = 0;
-                    for (; s < nsteps - 2; s += 2) {
+                    int s = kr.lo;
+                    for (; s < kr.hi - 2; s += 2) {
                         read_words(wn, s + 1);
                         mma_i8_cols<kF, true, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, tile_off + (s + 2) * 8 * 1024);
                         read_words(w, s + 2);
                         mma_i8_cols<kF, true, true>(A1, Bc, wn, w[0], bsh, acc, jrsrc, voff, tile_off + (s + 3) * 8 * 1024);
                     }
                     // the last two steps: no J left to fetch
-                    read_words(wn, nsteps - 1);
+                    read_words(wn, kr.hi - 1);
                     mma_i8_cols<kF, false, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, 0);
                     if (p == 0) {
                         if (more) rowv_next = fetch_rows(a.prob, next_tile);
-                        prefetch_counters<kF, kFp4>(cnt, is_lane, np);
+                        if (lead) prefetch_counters<kF, kFp4>(cnt, is_lane, np);
                     }
                     mma_i8_cols<kF, false, false>(A1, Bc, wn, 0u, bsh, acc, jrsrc, voff, 0);
+                }
+            }
+
+            if (share) {
+                // The other waves' partial sums pass through LDS to wave 0, which adds them to its own.  They are
+                // integers (with fp4 operands fp32 values below 2^22 in magnitude, as every partial sum of a row's
+                // product is), so the sum is exact in any order.
+                constexpr int kV = 8 * kF;   // 16-byte vectors of accumulators per lane
+                // vector q: acc[q / kF][q % kF] (16 x 16 tiles), or elements 4 (q % 4) .. + 3 of
+                // accw[(q / 4) / kNCB][(q / 4) % kNCB] (32 x 32 tiles)
+                auto get = [&](const int q) -> v4i {
+                    if constexpr (kWideT || kWideI) {
+                        const v16i& x = accw[(q / 4) / kNCB][(q / 4) % kNCB];
+                        const int e = 4 * (q % 4);
+                        return v4i{x[e], x[e + 1], x[e + 2], x[e + 3]};
+                    } else {
+                        return acc[q / kF][q % kF];
+                    }
+                };
+                auto add = [&](const int q, const v4i o) {
+                    v4i r;
+                    const v4i m = get(q);
+                    if constexpr (kFp4)
+                        r = __builtin_bit_cast(v4i, __builtin_bit_cast(v4f, m) + __builtin_bit_cast(v4f, o));
+                    else
+                        r = m + o;
+                    if constexpr (kWideT || kWideI) {
+                        v16i& x = accw[(q / 4) / kNCB][(q / 4) % kNCB];
+                        const int e = 4 * (q % 4);
+                        x[e] = r[0];
+                        x[e + 1] = r[1];
+                        x[e + 2] = r[2];
+                        x[e + 3] = r[3];
+                    } else {
+                        acc[q / kF][q % kF] = r;
+                    }
+                };
+                if (wave != 0) {
+#pragma unroll
+                    for (int q = 0; q < kV; ++q) red[((size_t)(wave - 1) * kV + q) * 64 + lane] = get(q);
+                }
+                __syncthreads();
+                if (wave != 0) return;
+#pragma unroll
+                for (int w = 1; w < kWaves; ++w) {
+#pragma unroll
+                    for (int q = 0; q < kV; ++q) add(q, red[((size_t)(w - 1) * kV + q) * 64 + lane]);
                 }
             }
 
@@ -1280,7 +1377,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 if constexpr (kWideT || kWideI) fused_epilogue<false, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
                 else fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             }
-        
         };
         // Tiles go to the waves in turn.  With 128-column blocks, when whole rounds of the four waves leave one
         // or two tiles over, those are split into column halves (4 fragments, all 128 rows each), one per wave,
@@ -1304,10 +1400,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                           last_full ? half_tile : tile + kWaves);
             }
             if (has_half) tile_body(std::integral_constant<int, kNBF / 2>{}, half_tile, (wave & 1) * (kNBF / 2), false, 0);
+        } else if (kSplit && kNBF == 2 && a.split_k == 4) {
+            // a row group of one tile, whose K steps the four waves share
+            rowv_next = rowv_first;
+            if (tr.lo < tr.hi) tile_body(std::integral_constant<int, kNBF>{}, tr.lo, 0, false, 0);
         } else {
             // A wave without a tile (fewer tiles than waves) fetches the last tile's row vectors instead, so that
             // the load stays inside the row vectors; it never uses them.
-            rowv_next = fetch_rows(a.prob, tr.lo + wave < tr.hi ? tr.lo + wave : ntiles - 1);
+            rowv_next = kSplit ? rowv_first : fetch_rows(a.prob, tr.lo + wave < tr.hi ? tr.lo + wave : ntiles - 1);
             for (int tile = tr.lo + wave; tile < tr.hi; tile += kWaves)
                 tile_body(std::integral_constant<int, kNBF>{}, tile, 0, tile + kWaves < tr.hi, tile + kWaves);
         }
@@ -1327,7 +1427,8 @@ __global__ __launch_bounds__(kThreads, kNBF == 8 ? 1 : 2) void sweep_kernel(Swee
 // column block blockIdx.x / n_groups, so that with n_groups a multiple of the XCD count every column block's
 // copy of a row group runs on one XCD and their J rows meet in its L2.
 template <bool kFast, int kMode, int kNBF, bool kFp4>
-__global__ __launch_bounds__(kThreads, 2) void sweep_split_kernel(const SweepArgs* __restrict__ item, int t, int flags) {
+__global__ __launch_bounds__(kThreads, 2) void sweep_split_kernel(const SweepArgs* __restrict__ item, int t, int flags,
+                                                                   int q_t, int i0_t) {
     SweepArgs a = *item;
     const int cb = blockIdx.x / a.n_groups;
     const int g = blockIdx.x - cb * a.n_groups;
@@ -1343,6 +1444,8 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_split_kernel(const SweepArg
         return;
     }
     const bool update = (flags & kSplitUpdate) != 0;
+    a.split_q = q_t;
+    a.split_i0 = i0_t;
     a.t_begin = t;
     a.t_end = update ? t + 1 : t;
     a.final_pass = update ? 0 : 1;
@@ -1631,10 +1734,15 @@ hipError_t launch_sweep_batch(const SweepArgs* items, const uint32_t* work, int 
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int t, int flags, hipStream_t stream) {
+hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int t, int flags, const int32_t* jperp,
+                              const int32_t* i0, hipStream_t stream) {
+    const int q_t = (flags & kSplitUpdate) ? jperp[t] : 0;
+    const int i0_t = (flags & kSplitUpdate) ? i0[t] : 0;
     const hipError_t ce = configure_sweep_kernels();
     if (ce != hipSuccess) return ce;
-    const size_t lds = (flags & kSplitRun) ? sweep_lds_bytes(host.prob.np, host.delay, host.nb) : 0;
+    const size_t lds = (flags & kSplitRun) ? sweep_lds_bytes(host.prob.np, host.delay, host.nb) +
+                                                 (host.split_k == 4 ? split_k_lds_bytes(host.nb) : 0)
+                                           : 0;
     // row groups (init, run), then one closing workgroup per column block (close)
     const int n_rows = (flags & (kSplitInit | kSplitRun)) ? host.n_cb * host.n_groups : 0;
     const int n_close = (flags & kSplitClose) && !(flags & kSplitInit) ? host.n_cb : 0;
@@ -1644,7 +1752,7 @@ hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int 
 #define SSQA_LAUNCH_SPLIT(v, al, mo, nbf, f4)                                                                   \
     case v:                                                                                                   \
         if constexpr (nbf != 8) {                                                                             \
-            hipLaunchKernelGGL((sweep_split_kernel<al, mo, nbf, f4>), grid, block, lds, stream, item, t, flags); \
+            hipLaunchKernelGGL((sweep_split_kernel<al, mo, nbf, f4>), grid, block, lds, stream, item, t, flags, q_t, i0_t); \
             break;                                                                                            \
         } else {                                                                                              \
             return hipErrorInvalidValue;                                                                      \

@@ -1,8 +1,9 @@
 """GPU tests of the row-split form of a plain anneal (ssqa_anneal with split_rows): every trial's rows spread
 over row groups of workgroups, one launch per cycle.  Forced (split_rows = 1) it gives the persistent form's
 results (split_rows = -1) bit for bit (best, first hit, energy trace, final counters) for both operand types,
-delays 0 to 2, both coupling modes, the general epilogue, 32- and 64-column blocks and zero cycles; on small
-cases both forms equal the oracle, SSA's (R = 1, Eq. 2) included.  An SSA-shaped anneal (N = 2500, R = 1)
+delays 0 to 2, both coupling modes, the general epilogue, 32- and 64-column blocks, zero cycles and groups of
+one tile whose K steps the workgroup's four waves share (partial sums added through LDS); on small cases both
+forms equal the oracle, SSA's (R = 1, Eq. 2) included.  An SSA-shaped anneal (N = 2500, R = 1)
 left to the automatic choice equals both forced forms."""
 
 import sys
@@ -48,6 +49,9 @@ def _same(a, b):
     (1300, 1, 100, 40, 0, 0, 1, 4, 64),    # SSA-shaped: R = 1, d = 0, 11 tiles (last group of 3)
     (300, 16, 7, 20, 1, 1, 2, 30, 32),     # 3 tiles in one group, alpha = 2, int8
     (520, 32, 3, 0, 1, 0, 1, 4, 64),       # zero cycles: sigma(0)'s energy only
+    (1100, 2, 20, 12, 1, 1, 3, 300, 32),   # int8 on two planes, the four waves sharing each tile's 18 K steps
+    (1900, 4, 16, 10, 2, 0, 1, 4, 32),     # fp4 at the fewest K steps the waves share (16), d = 2
+    (2100, 1, 40, 8, 0, 1, 1, 4, 32),      # fp4, 24 K steps over the waves, d = 0, both neighbours
 ])
 def test_forced_split_equals_persistent(lib, n, R, T, SC, delay, mode, alpha, j_max, bc):
     _note(f"case split anneal n={n} R={R} T={T} SC={SC} d={delay} mode={mode} alpha={alpha} columns={bc}")
