@@ -916,7 +916,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
     uint32_t* colinfo = reinterpret_cast<uint32_t*>(best_l + kNB);   // [kNB]
     int32_t* rowst = reinterpret_cast<int32_t*>(colinfo + kNB);      // [kWaves][256]
-    v4i* red = reinterpret_cast<v4i*>(rowst + kWaves * 256);          // [kWaves - 1][kNB / 2][64] (split_k = 4)
+    v4i* red = reinterpret_cast<v4i*>(rowst + kWaves * 256);          // [3 kNB / 2][64] v4i (split_k = 4)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1011,10 +1011,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             int8_t* is_lane = is_wg + (size_t)(tcol + 16 * foff) * np + tile * kTileRows + 32 * tg;
             const int voff = tl * 16;
             // A row-split group of one tile with split_k = 4 (32-column blocks, which have the registers to spare):
-            // the four waves share its K steps (k_share); wave 0 starts from the staged constants, adds the
-            // others' partial sums and alone runs the epilogue.
+            // the four waves share its K steps (k_share); wave 0 starts from the staged constants, and waves 0
+            // and 1 each add the others' partial sums of one column fragment and run its epilogue.
             const bool share = kSplit && kNBF == 2 && a.split_k == 4;
             const bool lead = !share || wave == 0;
+            // The epilogue's counters, fetched during the last K steps: every fragment's, or with `share` the
+            // wave's own fragment's (waves 0 and 1) into slot 0.
+            auto prefetch_epi = [&]() {
+                if (!share) prefetch_counters<kF, kFp4>(cnt, is_lane, np);
+                else if (wave < kF) load_counters<kFp4>(cnt[0], is_lane, np, wave);
+            };
             if constexpr (kWideT) {
                 // Field product on the fp4 copy of J (the same layout and exactness argument as below) with
                 // 32 x 32 x 64 MFMAs: per K step of 128, row blocks rb < 4 of 32 rows, column blocks cb < kNCB
@@ -1163,7 +1169,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 read_words(wn, kr.hi - 1);
                 mma_fp4_cols<kF, false, true>(A0, Bc, w, wn[0], accf, j4rsrc, voff, 0);
                 if (more) rowv_next = fetch_rows(a.prob, next_tile);
-                if (lead) prefetch_counters<kF, kFp4>(cnt, is_lane, np);
+                prefetch_epi();
                 mma_fp4_cols<kF, false, false>(A1, Bc, wn, 0u, accf, j4rsrc, voff, 0);
 #pragma unroll
                 for (int ai = 0; ai < 8; ++ai)
@@ -1284,56 +1290,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                     mma_i8_cols<kF, false, true>(A0, Bc, w, wn[0], bsh, acc, jrsrc, voff, 0);
                     if (p == 0) {
                         if (more) rowv_next = fetch_rows(a.prob, next_tile);
-                        if (lead) prefetch_counters<kF, kFp4>(cnt, is_lane, np);
+                        prefetch_epi();
                     }
                     mma_i8_cols<kF, false, false>(A1, Bc, wn, 0u, bsh, acc, jrsrc, voff, 0);
-                }
-            }
-
-            if (share) {
-                // The other waves' partial sums pass through LDS to wave 0, which adds them to its own.  They are
-                // integers (with fp4 operands fp32 values below 2^22 in magnitude, as every partial sum of a row's
-                // product is), so the sum is exact in any order.
-                constexpr int kV = 8 * kF;   // 16-byte vectors of accumulators per lane
-                // vector q: acc[q / kF][q % kF] (16 x 16 tiles), or elements 4 (q % 4) .. + 3 of
-                // accw[(q / 4) / kNCB][(q / 4) % kNCB] (32 x 32 tiles)
-                auto get = [&](const int q) -> v4i {
-                    if constexpr (kWideT || kWideI) {
-                        const v16i& x = accw[(q / 4) / kNCB][(q / 4) % kNCB];
-                        const int e = 4 * (q % 4);
-                        return v4i{x[e], x[e + 1], x[e + 2], x[e + 3]};
-                    } else {
-                        return acc[q / kF][q % kF];
-                    }
-                };
-                auto add = [&](const int q, const v4i o) {
-                    v4i r;
-                    const v4i m = get(q);
-                    if constexpr (kFp4)
-                        r = __builtin_bit_cast(v4i, __builtin_bit_cast(v4f, m) + __builtin_bit_cast(v4f, o));
-                    else
-                        r = m + o;
-                    if constexpr (kWideT || kWideI) {
-                        v16i& x = accw[(q / 4) / kNCB][(q / 4) % kNCB];
-                        const int e = 4 * (q % 4);
-                        x[e] = r[0];
-                        x[e + 1] = r[1];
-                        x[e + 2] = r[2];
-                        x[e + 3] = r[3];
-                    } else {
-                        acc[q / kF][q % kF] = r;
-                    }
-                };
-                if (wave != 0) {
-#pragma unroll
-                    for (int q = 0; q < kV; ++q) red[((size_t)(wave - 1) * kV + q) * 64 + lane] = get(q);
-                }
-                __syncthreads();
-                if (wave != 0) return;
-#pragma unroll
-                for (int w = 1; w < kWaves; ++w) {
-#pragma unroll
-                    for (int q = 0; q < kV; ++q) add(q, red[((size_t)(w - 1) * kV + q) * 64 + lane]);
                 }
             }
 
@@ -1359,10 +1318,48 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             ctx.alpha = a.alpha;
             ctx.coff = 16 * foff;
             ctx.ncols = kNB;
+            // The column fragments this wave finishes: [ef, ef + efn).
+            int ef = foff, efn = kF;
+            v4i acc1[8][1];       // with `share`: the summed accumulators of fragment `wave`
+            if constexpr (kSplit && kNBF == 2) {
+                if (share) {
+                    // Waves 2 and 3 pass all their partial sums through LDS, waves 0 and 1 the fragment the other
+                    // one finishes; each of waves 0 and 1 then adds the three partial sums of its fragment to its
+                    // own.  They are integers (with fp4 operands fp32 values below 2^22 in magnitude, as every
+                    // partial sum of a row's product is), so the sum is exact in any order.
+                    static_assert(kF == 2 && !(kWideT || kWideI), "shared tiles take 16 x 16 tiles of 32 columns");
+                    constexpr int kV = 8 * kF;   // 16-byte vectors of accumulators per lane
+                    auto slot = [&](const int i) -> v4i& { return red[(size_t)i * 64 + lane]; };
+                    if (wave >= kF) {
+#pragma unroll
+                        for (int q = 0; q < kV; ++q) slot((wave - kF) * kV + q) = acc[q / kF][q % kF];
+                    } else {
+#pragma unroll
+                        for (int ai = 0; ai < 8; ++ai) slot(2 * kV + 8 * wave + ai) = wave == 0 ? acc[ai][1] : acc[ai][0];
+                    }
+                    __syncthreads();
+                    if (wave >= kF) return;
+#pragma unroll
+                    for (int ai = 0; ai < 8; ++ai) {
+                        const v4i own = wave == 0 ? acc[ai][0] : acc[ai][1];
+                        const v4i o2 = slot(ai * kF + wave), o3 = slot(kV + ai * kF + wave);
+                        const v4i o1 = slot(2 * kV + 8 * (1 - wave) + ai);
+                        if constexpr (kFp4)
+                            acc1[ai][0] = __builtin_bit_cast(
+                                v4i, (__builtin_bit_cast(v4f, own) + __builtin_bit_cast(v4f, o1)) +
+                                         (__builtin_bit_cast(v4f, o2) + __builtin_bit_cast(v4f, o3)));
+                        else
+                            acc1[ai][0] = (own + o1) + (o2 + o3);
+                    }
+                    ef = wave;
+                    efn = 1;
+                    ctx.coff = 16 * wave;
+                }
+            }
             if (update) {
                 // One Philox block per column (lane c computes columns c, c + 64, ...), shared through LDS
                 // within the wave.
-                for (int c = 16 * foff + lane; c < 16 * (foff + kF); c += 64) {
+                for (int c = 16 * ef + lane; c < 16 * (ef + efn); c += 64) {
                     const uint32_t mine = colinfo[c];
                     const Philox4 x = philox4x32_10((uint32_t)(t + 1), (uint32_t)tile, (mine >> 16) & 0xFFu,
                                                     (uint32_t)b0 + ((mine >> 24) & 0x7Fu), a.key0, a.key1);
@@ -1371,9 +1368,23 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if constexpr (kSplit && kNBF == 2) {
+                    if (share) {
+                        v4i cnt1[1][2] = {{cnt[0][0], cnt[0][1]}};
+                        fused_epilogue<true, kFast, kMode, 1, kFp4>(acc1, cnt1, ctx);
+                        return;
+                    }
+                }
                 if constexpr (kWideT || kWideI) fused_epilogue<true, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
                 else fused_epilogue<true, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             } else {
+                if constexpr (kSplit && kNBF == 2) {
+                    if (share) {
+                        v4i cnt1[1][2] = {{cnt[0][0], cnt[0][1]}};
+                        fused_epilogue<false, kFast, kMode, 1, kFp4>(acc1, cnt1, ctx);
+                        return;
+                    }
+                }
                 if constexpr (kWideT || kWideI) fused_epilogue<false, kFast, kMode, kF, kFp4, true>(accw, cnt, ctx);
                 else fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             }
