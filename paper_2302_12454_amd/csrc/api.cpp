@@ -395,12 +395,11 @@ static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_param
     a.final_pass = 1;
     SweepArgs* d_args = reinterpret_cast<SweepArgs*>(base + o_item);
     {
-        // schedules and arguments through pinned staging (no host wait); the energy slots start at zero
+        // schedules and arguments through pinned staging (no host wait); the init launch clears the energy slots
         const void* srcs[3] = {pa->jperp, pa->i0, &a};
         const size_t sizes[3] = {(size_t)SC * 4, (size_t)SC * 4, sizeof(SweepArgs)};
         if (SC > 0) e = staged_upload(prob->device, d_sched, srcs, sizes, 2, stream);
         if (e == hipSuccess) e = staged_upload(prob->device, d_args, srcs + 2, sizes + 2, 1, stream);
-        if (e == hipSuccess) e = hipMemsetAsync(a.e_sum, 0, esum_bytes, stream);
     }
     const int32_t *jp = pa->jperp, *ip = pa->i0;
     if (e == hipSuccess) e = launch_sweep_split(d_args, a, 0, kSplitInit, jp, ip, stream);

@@ -724,7 +724,7 @@ __device__ __forceinline__ TileRange k_share(int ns, int wave) {
 }
 
 // sigma(0) and Is(0) of group g's rows of column block cb from the random stream (tag 0), into the ring slots
-// of sigma(0) and sigma(-s), s = 1..d; group 0 also resets the block's best energies and first hits.
+// of sigma(0) and sigma(-s), s = 1..d; group 0 also resets the block's best energies, first hits and energy sums.
 template <int kNB>
 __device__ void split_init_state(const SweepArgs& a, const int cb, const int g) {
     const int np = a.prob.np, words = np / 32, npl = a.delay + 2;
@@ -760,7 +760,7 @@ __device__ void split_init_state(const SweepArgs& a, const int cb, const int g) 
             dst[1] = hi;
         }
     }
-    if (g == 0)
+    if (g == 0) {
         for (int lb = threadIdx.x; lb < a.tpw; lb += kThreads) {
             const int b = b0 + lb;
             if (b < a.T) {
@@ -768,6 +768,13 @@ __device__ void split_init_state(const SweepArgs& a, const int cb, const int g) 
                 a.first_hit[b] = -1;
             }
         }
+        // both energy-sum slots of the block start at zero (a kernel store, not a memset, so that a caller may
+        // capture the launches in a graph)
+        for (int c = threadIdx.x; c < kNB; c += kThreads) {
+            a.e_sum[(size_t)cb * kNB + c] = 0;
+            a.e_sum[(size_t)(a.n_cb + cb) * kNB + c] = 0;
+        }
+    }
 }
 
 // Cycle t of column block cb, once every row group has added its energy sums (the previous launch): each
