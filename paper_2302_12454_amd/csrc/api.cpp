@@ -345,6 +345,8 @@ static int plain_split_columns(const ssqa_problem* prob, const ssqa_anneal_param
     int nb = pa->block_columns;
     if (nb == 0) nb = fits(32) && (blocks(32) <= kSplitMaxBlocks || !fits(64)) ? 32 : 64;
     if (nb > 64 || !fits(nb)) return 0;
+    // a forced split of very many trials keeps the persistent form rather than a grid past 2^30 workgroups
+    if ((long long)blocks(nb) * (np / kTileRows + 16) > (1LL << 30)) return 0;
     if (pa->split_rows > 0) return np >= pa->split_rows ? nb : 0;
     return np >= kSplitPlainRows && blocks(nb) <= kSplitMaxBlocks ? nb : 0;
 }
