@@ -1396,11 +1396,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
                 else fused_epilogue<false, kFast, kMode, kF, kFp4>(acc, cnt, ctx);
             }
         };
-        // Tiles go to the waves in turn.  With 128-column blocks, and 64-column ones with fp4 operands, when whole
-        // rounds of the four waves leave one or two tiles over, those are split into column halves (all 128 rows
-        // each), one per wave, so that the last round is shared instead of leaving two or three waves idle.
-        // 64-column int8 blocks (whose half tiles would spill) and 32-column blocks keep the plain loop.
-        constexpr bool kCanSplit = kNBF == 8 || (kNBF == 4 && kFp4 && !kSplit);
+        // Tiles go to the waves in turn.  When whole rounds of the four waves leave one or two tiles over, those
+        // are split into column halves (all 128 rows each), one per wave, so that the last round is shared instead
+        // of leaving two or three waves idle.  64-column int8 blocks (whose half tiles would spill) and the
+        // row-split form keep the plain loop.
+        constexpr bool kCanSplit = kNBF == 8 || (kNBF == 4 && kFp4 && !kSplit) || (kNBF == 2 && !kSplit);
         if constexpr (kCanSplit) {
             const int rounds = ntiles / kWaves, left = ntiles % kWaves;
             const bool split = left == 1 || left == 2;
