@@ -148,11 +148,12 @@ typedef struct ssqa_anneal_params {
                                   row groups of workgroups, one launch per cycle; Sec. 3.2's update of
                                   all N R spins per cycle is unchanged): 0 = automatic (taken from 1280
                                   padded rows when the trials fill at most 16 column blocks of 32 or 64
-                                  columns), -1 = never, k > 0 = from k padded rows on.  Only for fresh
-                                  runs to the end (start_cycle = 0, stop_cycle = 0 or cycles, no
-                                  checkpoint) on blocks of at most 64 columns (block_columns 0, 32 or
-                                  64); other runs, ssqa_anneal_noalloc, batches and served requests
-                                  ignore it.  A scheduling choice only: results do not depend on it */
+                                  columns, from 2048 when they fill at most 64), -1 = never, k > 0 =
+                                  from k padded rows on.  Only for fresh runs to the end (start_cycle
+                                  = 0, stop_cycle = 0 or cycles, no checkpoint) on blocks of at most
+                                  64 columns (block_columns 0, 32 or 64); other runs,
+                                  ssqa_anneal_noalloc, batches and served requests ignore it.  A
+                                  scheduling choice only: results do not depend on it             */
 } ssqa_anneal_params;
 
 typedef struct ssqa_anneal_outputs {

@@ -323,15 +323,18 @@ AnnealSizes anneal_sizes(const ssqa_problem* prob, const ssqa_anneal_params* pa)
 }
 
 // Padded rows from which an automatic plain anneal considers the row-split form.
-// Automatic row-split form: from this many padded rows, for anneals of at most kSplitMaxBlocks column blocks.
-// The persistent form gives each workgroup whole trials, so every workgroup streams all of J through its CU
-// once per cycle, whatever the number of workgroups; an anneal of few trials (SSA's R = 1, say) is then bound
-// by one CU's load rate.  The row-split form spreads each trial's rows over row groups of workgroups at the
-// price of one launch per cycle and sigma's exchange through device memory; on one MI355X it was measured
-// faster from N = 1225 (1280 padded rows) for 4 to 16 column blocks, slower at N = 625 and for 50 blocks of
-// 64 columns below N = 2025.
+// Automatic row-split form: from kSplitPlainRows padded rows for anneals of at most kSplitMaxBlocks column
+// blocks, and from kSplitWideRows for at most kSplitWideBlocks.  The persistent form gives each workgroup whole
+// trials, so every workgroup streams all of J through its CU once per cycle, whatever the number of
+// workgroups; an anneal of few trials (SSA's R = 1, say) is then bound by one CU's load rate.  The row-split
+// form spreads each trial's rows over row groups of workgroups at the price of one launch per cycle and
+// sigma's exchange through device memory.  On one MI355X it was measured faster from N = 1225 (1280 padded
+// rows) for 4 to 16 column blocks, slower at N = 625, and for 50 blocks of 64 columns slower at N = 1225 and
+// faster from N = 2025 (2048 padded rows: 19.0 against 23.7 us per cycle, at N = 2500 24.2 against 36.4).
 constexpr int kSplitPlainRows = 1280;
 constexpr int kSplitMaxBlocks = 16;
+constexpr int kSplitWideRows = 2048;
+constexpr int kSplitWideBlocks = 64;
 
 // Column-block width of the row-split form for a plain anneal (ssqa_anneal_params.split_rows), or 0 for the
 // persistent form.  Blocks hold whole trials: 32 columns while that gives few enough blocks (a narrower block
@@ -348,7 +351,9 @@ static int plain_split_columns(const ssqa_problem* prob, const ssqa_anneal_param
     // a forced split of very many trials keeps the persistent form rather than a grid past 2^30 workgroups
     if ((long long)blocks(nb) * (np / kTileRows + 16) > (1LL << 30)) return 0;
     if (pa->split_rows > 0) return np >= pa->split_rows ? nb : 0;
-    return np >= kSplitPlainRows && blocks(nb) <= kSplitMaxBlocks ? nb : 0;
+    const int n_cb = blocks(nb);
+    const bool pays = (np >= kSplitPlainRows && n_cb <= kSplitMaxBlocks) || (np >= kSplitWideRows && n_cb <= kSplitWideBlocks);
+    return pays ? nb : 0;
 }
 
 // The row-split form of a fresh anneal run to the end: whole trials per column block (nb / R each), the
