@@ -112,8 +112,8 @@ inline int split_groups(int np, int xcds, int group_tiles = kGroupTiles) {
     return (g + xcds - 1) / xcds * xcds;
 }
 
-// LDS of a row-split launch with split_k = 4 beyond sweep_lds_bytes: three waves' partial accumulators
-// (2 nb 32-bit words per lane) for the fourth to add.
+// LDS of a row-split launch with split_k = 4 beyond sweep_lds_bytes: the partial sums the four waves pass
+// each other, as much as three waves' accumulators (2 nb 32-bit words per lane each).
 inline size_t split_k_lds_bytes(int nb) { return (size_t)3 * 64 * 2 * nb * 4; }
 
 // Flags of one sweep_split_kernel launch at cycle t; its grid is n_cb x n_groups row-group workgroups (init,
