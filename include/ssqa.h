@@ -152,8 +152,10 @@ typedef struct ssqa_anneal_params {
                                   from k padded rows on.  Only for fresh runs to the end (start_cycle
                                   = 0, stop_cycle = 0 or cycles, no checkpoint) on blocks of at most
                                   64 columns (block_columns 0, 32 or 64); other runs,
-                                  ssqa_anneal_noalloc, batches and served requests ignore it.  A
-                                  scheduling choice only: results do not depend on it             */
+                                  ssqa_anneal_noalloc, batches and served requests ignore it.  The
+                                  split form enqueues one launch per cycle, so the call returns once
+                                  they are all queued (a few microseconds of host time per cycle).
+                                  A scheduling choice only: results do not depend on it          */
 } ssqa_anneal_params;
 
 typedef struct ssqa_anneal_outputs {
