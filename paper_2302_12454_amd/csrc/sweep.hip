@@ -955,7 +955,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
     const __amdgpu_buffer_rsrc_t j4rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(a.prob.J4), 0, kFp4 ? np * (a.prob.kp4 / 2) : 0, 0x00020000);
 
-    for (int t = a.t_begin; t <= a.t_end; ++t) {
+    // The row-split form runs one cycle (t_begin) per launch: its loop has one trip, which the compiler then
+    // lays out straight instead of hoisting the cycle's set-up into a preheader.
+    const int t_last = kSplit ? a.t_begin : a.t_end;
+    for (int t = a.t_begin; t <= t_last; ++t) {
         const bool update = t < a.t_end;
         if (!update && !a.final_pass) break;
         const int p_cur = t % npl;
