@@ -322,7 +322,6 @@ AnnealSizes anneal_sizes(const ssqa_problem* prob, const ssqa_anneal_params* pa)
     return z;
 }
 
-// Padded rows from which an automatic plain anneal considers the row-split form.
 // Automatic row-split form: from kSplitPlainRows padded rows for anneals of at most kSplitMaxBlocks column
 // blocks, and from kSplitWideRows for at most kSplitWideBlocks.  The persistent form gives each workgroup whole
 // trials, so every workgroup streams all of J through its CU once per cycle, whatever the number of
@@ -357,8 +356,8 @@ static int plain_split_columns(const ssqa_problem* prob, const ssqa_anneal_param
 }
 
 // The row-split form of a fresh anneal run to the end: whole trials per column block (nb / R each), the
-// block's rows in row groups of kGroupTiles tiles, one sweep_split_kernel launch per cycle (the launch
-// boundary is the cycle's barrier), sigma's ring of d + 2 bit planes and the energy sums in device memory.
+// block's rows in row groups of 1, 2 or 4 tiles, one sweep_split_kernel launch per cycle (the launch boundary
+// is the cycle's barrier), sigma's ring of d + 2 bit planes and the energy sums in device memory.
 static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_params* pa, const ssqa_anneal_outputs* out,
                                int nb, bool fp4, hipStream_t stream) {
     const int R = pa->replicas, T = pa->trials, SC = pa->cycles;
