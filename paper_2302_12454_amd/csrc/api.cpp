@@ -221,7 +221,10 @@ bool tile_legal(const ssqa_problem* prob, const ssqa_anneal_params* pa, int nb, 
 PlainLayout rule_layout(const ssqa_problem* prob, const ssqa_anneal_params* pa) {
     const int R = pa->replicas, T = pa->trials;
     const int target = 2 * device_cu_count(prob->device);
-    const bool fp4 = use_fp4(prob, pa);
+    // A one-tile problem (128 padded rows) takes int8 operands when J is one plane: the fp4 copy's K extent is
+    // at least 512 (four steps of 128, three of them padding), the plane's 128 (two steps of 64).  Measured
+    // 8-10 % faster at N = 25 and 100; from 256 padded rows fp4 is as fast or faster.
+    const bool fp4 = use_fp4(prob, pa) && !(pa->operand_format == 0 && prob->dev.np <= kTileRows && prob->dev.planes == 1);
     int nb = block_columns(prob, pa);
     // 128 columns per workgroup (one per CU, one wave per SIMD with 512 registers) feed each J fragment to twice
     // as many MFMAs; taken when wide blocks pay and still number two per CU.
