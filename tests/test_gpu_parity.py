@@ -239,6 +239,27 @@ def test_wide_blocks_fp4(lib, n, R, T, SC, delay, mode, fast):
     assert_same(wide, run_oracle(h, J, **kw))
 
 
+@pytest.mark.parametrize("n,R,T,SC,delay,mode,bc", [
+    (520, 8, 12, 20, 1, 0, 64),     # 5 tiles: one left over, split into two 32-column halves
+    (700, 16, 8, 16, 2, 1, 64),     # 6 tiles: two left over, four halves, d = 2, both ring neighbours
+    (1200, 4, 16, 10, 0, 0, 32),    # 10 tiles: two left over, 16-column halves, d = 0
+    (520, 2, 30, 20, 1, 1, 32),     # 5 tiles, 16-column halves, both ring neighbours
+])
+def test_leftover_tiles_in_column_halves(lib, n, R, T, SC, delay, mode, bc):
+    """fp4 operands on 64- and 32-column blocks whose last round of the four waves has one or two tiles: those
+    tiles are split into column halves, one per wave; the results equal the oracle bit for bit."""
+    _note(f"case leftover halves n={n} R={R} T={T} columns={bc} d={delay} mode={mode}")
+    h, J = random_ising(n, n + 7 * R, h_max=70, j_max=4)
+    rng = np.random.default_rng(n + bc)
+    q = rng.integers(-6, 7, size=SC)
+    i0 = rng.integers(8, 30, size=SC)
+    prob = lib.Problem(h, J)
+    assert prob.fp4_exact
+    kw = dict(replicas=R, trials=T, cycles=SC, q=q, i0=i0, alpha=1, noise=9, delay=delay, seed=n, mode=mode)
+    gpu = run_gpu(prob, block_columns=bc, operand_format=2, split_rows=-1, **kw)   # the persistent form
+    assert_same(gpu, run_oracle(h, J, **(kw | dict(trials=[0, T - 1]))), trial_idx=[0, T - 1])
+
+
 @pytest.mark.parametrize("n,R,T,SC,delay,mode,fast,j_max", [
     (300, 16, 20, 30, 1, 0, True, 9),      # byte-parallel epilogue, entries without fp4 codes, ragged tiles
     (700, 64, 5, 20, 2, 1, False, 127),    # general epilogue, |J| up to 127, both ring neighbours, d = 2
