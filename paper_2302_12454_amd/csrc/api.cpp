@@ -345,7 +345,7 @@ static int plain_split_columns(const ssqa_problem* prob, const ssqa_anneal_param
                                bool checkpoint, bool workspace) {
     if (pa->split_rows < 0 || workspace || checkpoint || t0 != 0 || t1 != pa->cycles) return 0;
     const int np = prob->dev.np, R = pa->replicas, T = pa->trials;
-    auto fits = [&](int nb) { return R <= nb && sweep_lds_bytes(np, pa->delay, nb) <= 160 * 1024; };
+    auto fits = [&](int nb) { return R <= nb && split_lds_bytes(np, nb) <= 160 * 1024; };
     auto blocks = [&](int nb) { return (T + nb / R - 1) / (nb / R); };
     int nb = pa->block_columns;
     if (nb == 0) nb = fits(32) && (blocks(32) <= kSplitMaxBlocks || !fits(64)) ? 32 : 64;
@@ -378,7 +378,7 @@ static hipError_t anneal_split(const ssqa_problem* prob, const ssqa_anneal_param
     // tile's K steps (at least four each), when their partial sums fit in LDS beside the bit planes.
     const int k_steps = fp4 ? prob->dev.kp4 / 128 : np / kStepK;
     const bool split_k = group_tiles == 1 && nb == 32 && k_steps >= 16 &&
-                         sweep_lds_bytes(np, pa->delay, nb) + split_k_lds_bytes(nb) <= 160 * 1024;
+                         split_lds_bytes(np, nb) + split_k_lds_bytes(nb) <= 160 * 1024;
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t o_sched = 0;
     const size_t o_is = align((size_t)2 * std::max(SC, 1) * 4);

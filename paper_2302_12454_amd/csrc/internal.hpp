@@ -107,6 +107,7 @@ struct SweepArgs {
 // Row tiles per group of the row-split form (at most one per wave), and the groups of a block: enough to cover
 // the tiles, rounded up to a multiple of the XCD count so that a row group's copies in every block share an XCD.
 constexpr int kGroupTiles = 4;
+constexpr int kGroupWords = 4 * kGroupTiles + 1;   // LDS words per column of a group's rows (one of padding)
 inline int split_groups(int np, int xcds, int group_tiles = kGroupTiles) {
     const int g = (np / kTileRows + group_tiles - 1) / group_tiles;
     return (g + xcds - 1) / xcds * xcds;
@@ -135,6 +136,9 @@ hipError_t launch_prepare_fp4(const void* J, int elem, int32_t n, int32_t np, in
 hipError_t configure_sweep_kernels();
 // Dynamic LDS of one sweep workgroup for padded size np, delay d and nb columns.
 size_t sweep_lds_bytes(int np, int delay, int nb);
+// Dynamic LDS of a row-split launch (sweep_split_kernel): sigma(t) of the block, the group's rows of sigma(t - d)
+// and sigma(t + 1) (kGroupWords words per column), and the rest as in sweep_lds_bytes.
+size_t split_lds_bytes(int np, int nb);
 // Kernel variant index of (alpha == 1, coupling mode, nb, fp4 operands); kSweepVariants in total.
 constexpr int kSweepVariants = 24;
 int sweep_variant(bool fast, int mode, int nb, bool fp4);

@@ -314,6 +314,9 @@ struct EpilogueCtx {
     // per-row part of the energy term (see sweep_block for what each holds).
     const int32_t* rows;
     int np, cstride, tile, wave, lane;
+    // sigma(t - d) and sigma(t + 1): word w of column c at c * cstride_dn + w - dn_off (the whole plane, or in the
+    // row-split form the group's rows only)
+    int cstride_dn, dn_off;
     int coff;                 // first column of the fragments this call covers (0, or 64 for a column half)
     int ncols;                // columns per wave in the noise area (the block width)
     int two_n, two_q, i0, alpha;
@@ -388,7 +391,6 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
     // registers) across the K loop.
     int ln = x.lane;
     asm volatile("" : "+v"(ln));
-    constexpr int kNCB = kUnits / 2;
     auto ucol = [&](const int u) { return x.coff + (kWide ? 32 * (u >> 1) + (ln & 31) : 16 * u + (ln & 15)); };
     auto urun = [&](const int u) { return kWide ? 2 * (u & 1) + (ln >> 5) : (ln >> 4); };
     auto ucnt = [&](const int u) { return x.is_wg + (size_t)ucol(u) * x.np + x.tile * kTileRows + 32 * urun(u); };
@@ -427,8 +429,8 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
         if constexpr (!kAhead) info_u[u] = x.colinfo[c];
         nx_sig = ~x.pl_cur[c * x.cstride + word];
         if (kUpdate) {
-            nx_up = x.pl_del[(info_u[u] & 0xFFu) * x.cstride + word];
-            if (kMode == 1) nx_dn = x.pl_del[((info_u[u] >> 8) & 0xFFu) * x.cstride + word];
+            nx_up = x.pl_del[(info_u[u] & 0xFFu) * x.cstride_dn + word - x.dn_off];
+            if (kMode == 1) nx_dn = x.pl_del[((info_u[u] >> 8) & 0xFFu) * x.cstride_dn + word - x.dn_off];
             nx_noise = x.noise_lds[(x.wave * x.ncols + c) * 4 + urun(u)];
         }
     };
@@ -507,7 +509,7 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
         if (kUpdate) {
             __builtin_nontemporal_store(is_lo, is_ptr);
             __builtin_nontemporal_store(is_hi, is_ptr + 1);
-            x.pl_next[c * x.cstride + word] = ~negbits;
+            x.pl_next[c * x.cstride_dn + word - x.dn_off] = ~negbits;
         }
         // Each lane adds its 32 rows' share: the lanes of a column meet in the LDS atomic, which needs no lane
         // index (a cross-lane shuffle would need one, and with every register taken the compiler reloads it
@@ -520,7 +522,9 @@ __device__ __forceinline__ void fused_epilogue(const AccT& acc, v4i (&cnt)[kUnit
 // Workgroup state shared by the sweep kernels: the sigma bit-plane ring and the per-column and per-trial
 // accumulators in LDS (layout in sweep_block).
 struct BlockLds {
-    uint32_t* planes;     // [npl][kNB][cstride] sigma bit planes, npl = ring length
+    uint32_t* planes;     // [npl][kNB][cstride] sigma bit planes, npl = ring length (row-split: sigma(t) only)
+    uint32_t* del_c;      // row-split form: [kNB][kGroupWords] the group's rows of sigma(t - d)
+    uint32_t* next_c;     // row-split form: [kNB][kGroupWords] the group's rows of sigma(t + 1)
     int npl, plane_words, cstride;
     int32_t* e_acc;       // [kNB]
     int32_t* hit_l;       // [kNB]
@@ -821,7 +825,7 @@ __device__ void split_close_cycle(const SweepArgs& a, const int cb, const int t)
 template <int kNB>
 __device__ __forceinline__ void split_block_init(const SweepArgs& a, const int cb, const TileRange tr, const BlockLds& L) {
     const int np = a.prob.np, words = np / 32;
-    const int npl = L.npl, plane_words = L.plane_words, cstride = L.cstride;
+    const int npl = L.npl, cstride = L.cstride;
     const int R = a.R, b0 = cb * a.tpw;
     const int t = a.t_begin;
     const int tid = threadIdx.x;
@@ -853,7 +857,7 @@ __device__ __forceinline__ void split_block_init(const SweepArgs& a, const int c
             const int u = u0 + i * kThreads;
             if (u < n4) {
                 const int c = 4 * u / words;
-                uint32_t* dst = L.planes + p_cur * plane_words + c * cstride + (4 * u - c * words);
+                uint32_t* dst = L.planes + c * cstride + (4 * u - c * words);
                 dst[0] = v[i].x;
                 dst[1] = v[i].y;
                 dst[2] = v[i].z;
@@ -861,14 +865,15 @@ __device__ __forceinline__ void split_block_init(const SweepArgs& a, const int c
             }
         }
     }
-    if (a.delay > 0) {
+    {
+        // the group's rows of sigma(t - d) (of sigma(t) when d = 0)
         const int p_del = (t - a.delay + npl) % npl;
         const uint32_t* dsrc = a.ring + ((size_t)p_del * a.n_cb + cb) * kNB * words;
         const int gw = 4 * (tr.hi - tr.lo);
         for (int u = tid; u < kNB * gw; u += kThreads) {
             const int c = u / gw;
-            const int w = 4 * tr.lo + (u - c * gw);
-            L.planes[p_del * plane_words + c * cstride + w] = dsrc[(size_t)c * words + w];
+            const int wl = u - c * gw;
+            L.del_c[c * kGroupWords + wl] = dsrc[(size_t)c * words + 4 * tr.lo + wl];
         }
     }
     __syncthreads();
@@ -887,8 +892,8 @@ __device__ __forceinline__ void split_block_close(const SweepArgs& a, const int 
         const int gw = 4 * (tr.hi - tr.lo);
         for (int u = threadIdx.x; u < kNB * gw; u += kThreads) {
             const int c = u / gw;
-            const int w = 4 * tr.lo + (u - c * gw);
-            dst[(size_t)c * words + w] = L.planes[p_next * L.plane_words + c * L.cstride + w];
+            const int wl = u - c * gw;
+            dst[(size_t)c * words + 4 * tr.lo + wl] = L.next_c[c * kGroupWords + wl];
         }
     }
     if (tr.hi > tr.lo) {
@@ -917,7 +922,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
     const int plane_words = kNB * cstride;
     const int npl = a.delay + 2;
     uint32_t* planes = lds;
-    uint32_t* noise_lds = lds + npl * plane_words;
+    // The row-split form holds sigma(t) of the whole block and only the group's rows of sigma(t - d) and
+    // sigma(t + 1) (kGroupWords words per column), so that large N keep two workgroups per CU.
+    uint32_t* del_c = lds + plane_words;
+    uint32_t* next_c = del_c + kNB * kGroupWords;
+    uint32_t* noise_lds = kSplit ? next_c + kNB * kGroupWords : lds + npl * plane_words;
     int32_t* e_acc = reinterpret_cast<int32_t*>(noise_lds + kWaves * kNB * 4);
     int32_t* hit_l = e_acc + kNB;
     long long* best_l = reinterpret_cast<long long*>(hit_l + kNB);
@@ -933,7 +942,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
     const int b0 = wg * a.tpw;
     int8_t* is_wg = a.is_state + (size_t)wg * kNB * np;
 
-    const BlockLds L{planes, npl, plane_words, cstride, e_acc, hit_l, best_l, colinfo};
+    const BlockLds L{planes, kSplit ? del_c : nullptr, kSplit ? next_c : nullptr, npl, plane_words, cstride,
+                     e_acc, hit_l, best_l, colinfo};
     // Row tiles of this workgroup: all of them, or the group's range in the row-split form.
     const TileRange tr = kSplit ? group_tiles(a, group) : TileRange{0, ntiles};
     // The row-split form fetches its first tile's row vectors ahead of the block state, so that they are on
@@ -986,9 +996,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
         const int row_add_h = adj_c + kAccOffset;
         const int row_add_e = -adj_c - kAccOffset;
         const uint32_t qflip = (kFast && q < 0) ? 0xFFFFFFFFu : 0u;
-        const uint32_t* pl_cur = planes + p_cur * plane_words;
-        const uint32_t* pl_del = planes + p_del * plane_words;
-        uint32_t* pl_next = planes + p_next * plane_words;
+        const uint32_t* pl_cur = kSplit ? planes : planes + p_cur * plane_words;
+        const uint32_t* pl_del = kSplit ? del_c : planes + p_del * plane_words;
+        uint32_t* pl_next = kSplit ? next_c : planes + p_next * plane_words;
 
         // The work of one tile for kF column fragments starting at fragment foff: all of them (kF = kNBF,
         // foff = 0), or one column half of a 128-column block (kF = 4, foff = 0 or 4).
@@ -1318,6 +1328,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const int wg, co
             ctx.rows = rows_w;
             ctx.np = np;
             ctx.cstride = cstride;
+            ctx.cstride_dn = kSplit ? kGroupWords : cstride;
+            ctx.dn_off = kSplit ? 4 * tr.lo : 0;
             ctx.tile = tile;
             ctx.wave = wave;
             ctx.lane = lane;
@@ -1665,6 +1677,11 @@ hipError_t launch_qmc_energy(const DeviceProblem& prob, const int8_t* counters, 
     return hipGetLastError();
 }
 
+size_t split_lds_bytes(int np, int nb) {
+    return (size_t)nb * (np / 32 + 1) * 4 + (size_t)2 * nb * kGroupWords * 4 + (size_t)kWaves * nb * 16 +
+           (size_t)nb * 4 * 2 + (size_t)nb * 8 + (size_t)nb * 4 + (size_t)kWaves * 256 * 4;
+}
+
 size_t sweep_lds_bytes(int np, int delay, int nb) {
     const size_t plane_words = (size_t)nb * (np / 32 + 1);
     return (size_t)(delay + 2) * plane_words * 4 + (size_t)kWaves * nb * 16 + (size_t)nb * 4 * 2 + (size_t)nb * 8 +
@@ -1761,7 +1778,7 @@ hipError_t launch_sweep_split(const SweepArgs* item, const SweepArgs& host, int 
     const int i0_t = (flags & kSplitUpdate) ? i0[t] : 0;
     const hipError_t ce = configure_sweep_kernels();
     if (ce != hipSuccess) return ce;
-    const size_t lds = (flags & kSplitRun) ? sweep_lds_bytes(host.prob.np, host.delay, host.nb) +
+    const size_t lds = (flags & kSplitRun) ? split_lds_bytes(host.prob.np, host.nb) +
                                                  (host.split_k == 4 ? split_k_lds_bytes(host.nb) : 0)
                                            : 0;
     // row groups (init, run), then one closing workgroup per column block (close)
