@@ -118,3 +118,24 @@ def test_ssa_shape_takes_split_form_by_itself(lib):
     _same(auto, whole)
     assert_same(auto, run_oracle(h, J, **(kw | dict(trials=[0]))), trial_idx=[0])
     prob.close()
+
+
+def test_ssa_table4_shape_long_run_against_oracle(lib):
+    """Table 4's SSA at N = 2500 (GI n = 50 at scale 4, R = 1, 100 trials) for its first 1000 cycles of the
+    I_0 schedule (Section 4.4): the automatic row-split form with the four waves sharing each tile's K steps
+    runs 1000 launches, reusing the ring slots and energy-sum slots hundreds of times; trials 0 and 99 are
+    replayed by the oracle's SSA (Eq. 2), energy trace and final counters."""
+    _note("case SSA N=2500 T=100 SC=1000 against the oracle")
+    h, J, e_star = gi_case(50, 50, scale=4)
+    SC = 1000
+    i0 = ssqa.scaled(ssqa.ssa_i0_schedule(SC, 10, Fraction(1, 2), 1, 16), 4)
+    prob = lib.Problem(h, J)
+    assert prob.padded == 2560 and prob.fp4_exact
+    gpu = run_gpu(prob, replicas=1, trials=100, cycles=SC, q=np.zeros(SC, int), i0=i0, alpha=1, noise=4,
+                  delay=1, seed=50, target=e_star)
+    sampled = [0, 99]
+    e_ref, Is_ref, _ = ssqa.ssa_anneal(h, J, sampled, SC, i0, 1, 4, seed=50, chains=[0])
+    assert np.array_equal(gpu["trace"][:, sampled, :], e_ref)
+    assert np.array_equal(gpu["Is"][sampled], Is_ref)
+    assert np.array_equal(gpu["best"][sampled], e_ref.min(axis=(0, 2)))
+    prob.close()
