@@ -139,3 +139,22 @@ def test_ssa_table4_shape_long_run_against_oracle(lib):
     assert np.array_equal(gpu["Is"][sampled], Is_ref)
     assert np.array_equal(gpu["best"][sampled], e_ref.min(axis=(0, 2)))
     prob.close()
+
+
+def test_ssqa_table4_shape_split_against_oracle(lib):
+    """Table 4's SSQA at N = 2500 (GI n = 50, R = 25, 100 trials, Table 2 schedules): the automatic choice is the
+    row-split form on 50 blocks of 64 columns (groups of four tiles); over its first 200 cycles trials 0 and
+    99 equal the oracle (energy trace, best, first hit, final counters), and all trials equal the persistent
+    form."""
+    _note("case SSQA N=2500 R=25 T=100 SC=200 split against the oracle")
+    h, J, e_star = gi_case(50, 50)
+    SC = 200
+    q, i0, noise = paper_schedules(SC, tau=50)
+    prob = lib.Problem(h, J)
+    kw = dict(replicas=25, trials=100, cycles=SC, q=q, i0=i0, alpha=1, noise=noise, delay=1, seed=50,
+              target=e_star)
+    auto = run_gpu(prob, **kw)
+    whole = run_gpu(prob, split_rows=-1, **kw)
+    _same(auto, whole)
+    assert_same(auto, run_oracle(h, J, **(kw | dict(trials=[0, 99]))), trial_idx=[0, 99])
+    prob.close()
