@@ -3,8 +3,9 @@ over row groups of workgroups, one launch per cycle.  Forced (split_rows = 1) it
 results (split_rows = -1) bit for bit (best, first hit, energy trace, final counters) for both operand types,
 delays 0 to 2, both coupling modes, the general epilogue, 32- and 64-column blocks, zero cycles and groups of
 one tile whose K steps the workgroup's four waves share (partial sums added through LDS); on small cases both
-forms equal the oracle, SSA's (R = 1, Eq. 2) included.  An SSA-shaped anneal (N = 2500, R = 1)
-left to the automatic choice equals both forced forms."""
+forms equal the oracle, SSA's (R = 1, Eq. 2) included.  An SSA-shaped anneal (N = 2500, R = 1) left to the
+automatic choice equals both forced forms, and Table 4's SSA and SSQA shapes at N = 2500 equal the oracle
+over hundreds of split launches."""
 
 import sys
 from fractions import Fraction
